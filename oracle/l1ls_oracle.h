@@ -1,0 +1,119 @@
+/*
+ * l1ls_oracle.h -- plain FP64 CPU oracle for the complex L1-regularised least
+ * squares problem (basis pursuit denoising) of Shi, Zhu, Yin and Bamler,
+ * "A fast and accurate basis pursuit denoising algorithm with application to
+ * super-resolving tomographic SAR" (arXiv 1805.01759).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU path under paper_1805_01759_amd/.
+ *
+ * Problem (Eq. (1) = Eq. (6), no factor 1/2 on the quadratic term):
+ *     min_x  F(x) = ||A x - b||_2^2 + lambda ||x||_1,   x in C^L,
+ * A in C^{N x L} row-major (A[n*L + l]), b in C^N, lambda > 0.
+ * Batched data: B is P x N pixel-major, X is P x L pixel-major.
+ * Complex values are C99 `double _Complex` (interleaved re, im), which is the
+ * memory layout of numpy complex128.
+ *
+ * Every function is a direct transcription of a definition or of the steps of
+ * Algorithm 1 (RBPG with backtracking) with one block (J = 1).  Where the
+ * paper is silent the reading used is stated at the function.
+ */
+#ifndef L1LS_ORACLE_H
+#define L1LS_ORACLE_H
+
+#include <complex.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef double _Complex ocplx;
+
+/* Lipschitz constant of grad f, f(x) = ||Ax - b||^2:  L_f = 2 lambda_max(A A^H).
+ * Cyclic Jacobi on the real symmetric 2N x 2N embedding of A A^H (whose
+ * spectrum is that of A A^H with every eigenvalue doubled in multiplicity). */
+double orc_lipschitz(int n, int l, const ocplx *A);
+
+/* Complex soft threshold  S_tau(v) = v * max(0, 1 - tau/|v|), elementwise;
+ * |v| <= tau (ties included) maps to 0.  Eq. (10) in complex form. */
+void orc_prox(int m, const ocplx *v, double tau, ocplx *out);
+
+/* F(x) = ||Ax-b||^2 + lambda ||x||_1  (Eq. (1)). */
+double orc_objective(int n, int l, const ocplx *A, const ocplx *b, double lambda,
+                     const ocplx *x);
+
+/* Natural KKT residual (gradient-mapping form):
+ *   KKT_nat(x) = L_f * max_l |x_l - S_{lambda/L_f}(x_l - g_l/L_f)_l| / lambda,
+ * with g = 2 A^H (A x - b).  Zero iff x is a minimiser. */
+double orc_kkt_nat(int n, int l, const ocplx *A, const ocplx *b, double lambda,
+                   double Lf, const ocplx *x);
+
+/* Subgradient KKT residual:
+ *   max_l { |g_l + lambda x_l/|x_l|| if x_l != 0 ;  max(0, |g_l| - lambda) if x_l = 0 } / lambda. */
+double orc_kkt_sub(int n, int l, const ocplx *A, const ocplx *b, double lambda,
+                   const ocplx *x);
+
+/* Duality gap F(x) - D(nu) with the dual point nu = s * 2(Ax - b),
+ * s = min(1, lambda / max_l |2 a_l^H (Ax - b)|),
+ * D(nu) = -||nu||^2/4 - Re(nu^H b)  (dual of Eq. (1), feasible for |a_l^H nu| <= lambda). */
+double orc_dual_gap(int n, int l, const ocplx *A, const ocplx *b, double lambda,
+                    const ocplx *x);
+
+/* Options of Algorithm 1 with J = 1 (full gradient). */
+typedef struct {
+    double alpha0;   /* initial step; <= 0 selects 1/(2 max_l ||a_l||^2)          */
+    double c_alpha;  /* backtracking factor C_alpha in (0,1)                        */
+    double tol;      /* stop when KKT_nat(x^k) <= tol                               */
+    int    max_iter; /* N_K                                                         */
+    int    backtracking; /* 0: fixed step alpha0                                    */
+    int    monotone;     /* 1: accept x-bar only if F(x-bar) <= F(x^k)               */
+} orc_rbpg_opts;
+
+typedef struct {
+    int    iters;       /* iterations performed                                      */
+    int    backtracks;  /* total step reductions                                     */
+    double alpha;       /* final step                                                */
+    double kkt_nat;     /* KKT_nat at the returned point                              */
+    double objective;   /* F at the returned point                                    */
+    int    converged;   /* 1 if kkt_nat <= tol                                        */
+} orc_rbpg_info;
+
+/* Algorithm 1 with one block, FP64.  x (length L) is the output; starts at 0. */
+void orc_rbpg(int n, int l, const ocplx *A, const ocplx *b, double lambda, double Lf,
+              const orc_rbpg_opts *opt, ocplx *x, orc_rbpg_info *info);
+
+/* Active-set damped Newton on the support of x, then the certificate.
+ * x is refined in place.  Returns the number of outer active-set rounds. */
+int orc_polish(int n, int l, const ocplx *A, const ocplx *b, double lambda, double Lf,
+               ocplx *x);
+
+/* Batched drivers, threads over pixels.  lambda has stride lambda_stride
+ * (0 => one scalar for all pixels).  Any diagnostic pointer may be NULL.
+ * nthreads <= 0 selects the number of online cores. */
+void orc_rbpg_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,
+                    const double *lambda, int64_t lambda_stride,
+                    const orc_rbpg_opts *opt, int nthreads, ocplx *X,
+                    int32_t *iters, double *kkt, int32_t *converged);
+
+/* The minimiser per pixel: Algorithm 1 to a tight stage tolerance, then the
+ * Newton polish, then the certificates (KKT_sub, KKT_nat, duality gap). */
+void orc_exact_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,
+                     const double *lambda, int64_t lambda_stride, int nthreads,
+                     ocplx *X, double *kkt_sub, double *kkt_nat, double *gap,
+                     double *objective);
+
+/* K iterations of the fixed-step accelerated proximal gradient map
+ * (Eqs. (11)-(12) with alpha constant, no backtracking, no monotone test),
+ * from x^0 = x^{-1} = 0, scalar lambda.  X is the K-th iterate. */
+void orc_unrolled_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,
+                        double lambda, double alpha, int K, int nthreads, ocplx *X);
+
+/* Number of threads the batched drivers use for nthreads <= 0. */
+int orc_default_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

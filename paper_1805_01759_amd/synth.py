@@ -1,0 +1,212 @@
+"""Seeded synthetic TomoSAR stacks (inputs only; none of the solver's arithmetic).
+
+Both the GPU path's tests/benchmark and the FP64 oracle draw their inputs from
+here.  The imaging model is Eq. (2) / Eq. (5) of arXiv 1805.01759 with no
+motion term: a pixel's measurement vector is
+    g_n = sum_k gamma_k exp(-j 2 pi xi_n s_k) + eps_n,   xi_n = 2 b_n / (lambda_w r),
+and A[n, l] = exp(-j 2 pi xi_n s_l) samples the same phase on a uniform
+elevation grid s_l.  (The paper writes exp(+j...); the sign convention only
+conjugates the problem.)  Scatterer amplitudes are CN(0, 1), the noise is
+CN(0, sigma^2) per acquisition with sigma^2 = 10^(-SNR/10), and the
+regularisation weight is lambda = sigma sqrt(2 N ln L).
+
+Randomness: numpy Philox.  Key = 1805_01759 + config id (+ stack id); every
+block of ``BLOCK`` pixels has its own counter offset, so any pixel range can be
+regenerated alone and gives the same values as the full stack.  Everything is
+generated in float64; ``to_device_dtypes`` rounds to complex64/float32 once,
+and the oracle upcasts those same rounded values.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+KEY = 1805_01759
+BLOCK = 4096
+WAVELENGTH = 0.031  # m (X band)
+RANGE = 7.0e5       # m
+
+
+@dataclasses.dataclass
+class Geometry:
+    n: int
+    l: int
+    baselines: np.ndarray  # (N,) metres
+    xi: np.ndarray         # (N,) cycles per metre
+    s: np.ndarray          # (L,) elevation grid, metres
+    A: np.ndarray          # (N, L) complex128
+
+    @property
+    def rayleigh(self) -> float:
+        """Elevation resolution from the realised aperture, lambda_w r / (2 (b_max - b_min))."""
+        return WAVELENGTH * RANGE / (2.0 * float(self.baselines.max() - self.baselines.min()))
+
+
+@dataclasses.dataclass
+class Spec:
+    cfg: int
+    n: int
+    l: int
+    p: int
+    bmax: float
+    s_lo: float
+    s_hi: float
+    model: str          # "c1" | "c2" | "c4" | "c5"
+    snr_db: float | None = 10.0
+
+
+SPECS = {
+    1: Spec(1, 15, 101, 1024, 250.0, -50.0, 50.0, "c1", 10.0),
+    2: Spec(2, 25, 256, 1 << 20, 300.0, -60.0, 60.0, "c2", None),
+    4: Spec(4, 50, 512, 1 << 22, 300.0, -60.0, 60.0, "c4", 10.0),
+    5: Spec(5, 25, 256, 1 << 18, 300.0, -60.0, 60.0, "c5", 10.0),
+}
+
+
+def _gen(cfg: int, stack: int, stream: int, block: int) -> np.random.Generator:
+    key = ((KEY + cfg) << 40) | (stack << 8) | stream
+    return np.random.Generator(np.random.Philox(key=key, counter=[0, 0, block, 0]))
+
+
+def make_geometry(cfg: int, n: int, l: int, bmax: float, s_lo: float, s_hi: float,
+                  stack: int = 0) -> Geometry:
+    g = _gen(cfg, stack, 0, 0)
+    b = g.uniform(-bmax, bmax, size=n)
+    xi = 2.0 * b / (WAVELENGTH * RANGE)
+    s = np.linspace(s_lo, s_hi, l)
+    A = np.exp(-2j * np.pi * np.outer(xi, s))
+    return Geometry(n, l, b, xi, s, A)
+
+
+def steering(xi: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """exp(-j 2 pi xi_n s) for an array of elevations s (shape (..., ) -> (..., N))."""
+    return np.exp(-2j * np.pi * np.multiply.outer(s, xi))
+
+
+def _cn(g, size, var=1.0):
+    return (g.standard_normal(size) + 1j * g.standard_normal(size)) * math.sqrt(var / 2.0)
+
+
+def _block_pixels(spec: Spec, geom: Geometry, block: int, count: int, stack: int):
+    """Pixels [block*BLOCK, block*BLOCK + count) of one stack."""
+    g = _gen(spec.cfg, stack, 1, block)
+    n, l = geom.n, geom.l
+    lo, hi = float(geom.s[0]), float(geom.s[-1])
+    # two scatterer slots per pixel; unused slots carry zero amplitude
+    amp = _cn(g, (count, 2))
+    elev = g.uniform(lo, hi, size=(count, 2))
+    xtrue_idx = np.full((count, 2), -1, np.int64)
+    if spec.model == "c2":
+        k = g.choice(3, size=count, p=[0.3, 0.5, 0.2])
+    else:
+        k = g.integers(0, 3, size=count)
+    if spec.model == "c4":
+        pair = g.uniform(size=count) < 0.4
+        kappa = g.uniform(0.3, 1.0, size=count)
+        ds = kappa * geom.rayleigh
+        mid = g.uniform(lo + ds / 2.0, hi - ds / 2.0)
+        zero_phase = g.uniform(size=count) < 0.1
+        e2 = np.stack([mid - ds / 2.0, mid + ds / 2.0], axis=1)
+        elev = np.where(pair[:, None], e2, elev)
+        k = np.where(pair, 2, k)
+        a1 = amp[:, 1]
+        same = np.abs(a1) * np.exp(1j * np.angle(amp[:, 0]))
+        amp[:, 1] = np.where(pair & zero_phase, same, a1)
+    if spec.model == "c5":
+        # on-grid scatterers, so that the true profile is an L-vector
+        idx = g.integers(0, l, size=(count, 2))
+        elev = geom.s[idx]
+        xtrue_idx = idx
+    amp = amp * (np.arange(2)[None, :] < k[:, None])
+    if spec.snr_db is None:
+        snr = g.uniform(0.0, 20.0, size=count)
+    else:
+        snr = np.full(count, spec.snr_db)
+    sigma2 = 10.0 ** (-snr / 10.0)
+    noise = _cn(g, (count, n)) * np.sqrt(sigma2)[:, None]
+    B = np.einsum("pk,pkn->pn", amp, steering(geom.xi, elev)) + noise
+    lam = np.sqrt(sigma2) * math.sqrt(2.0 * n * math.log(l))
+    meta = {"k": k, "elev": elev, "amp": amp, "snr_db": snr, "xtrue_idx": xtrue_idx}
+    return B, lam, meta
+
+
+def make_pixels(spec: Spec, geom: Geometry, p0: int = 0, p1: int | None = None,
+                stack: int = 0, with_meta: bool = False):
+    """B (P, N) complex128 and lambda (P,) float64 for pixels [p0, p1)."""
+    p1 = spec.p if p1 is None else p1
+    Bs, lams, metas = [], [], []
+    b0, b1 = p0 // BLOCK, (p1 - 1) // BLOCK
+    for blk in range(b0, b1 + 1):
+        start = blk * BLOCK
+        cnt = min(BLOCK, spec.p - start)
+        B, lam, meta = _block_pixels(spec, geom, blk, cnt, stack)
+        lo, hi = max(p0 - start, 0), min(p1 - start, cnt)
+        Bs.append(B[lo:hi])
+        lams.append(lam[lo:hi])
+        if with_meta:
+            metas.append({k: v[lo:hi] for k, v in meta.items()})
+    B = np.concatenate(Bs) if Bs else np.zeros((0, geom.n), np.complex128)
+    lam = np.concatenate(lams) if lams else np.zeros(0)
+    if not with_meta:
+        return B, lam
+    meta = {k: np.concatenate([m[k] for m in metas]) for k in metas[0]} if metas else {}
+    return B, lam, meta
+
+
+def make_config(cfg: int, p0: int = 0, p1: int | None = None, with_meta: bool = False,
+                p_override: int | None = None):
+    """Geometry and pixels of one single-stack configuration (1, 2, 4 or 5)."""
+    spec = dataclasses.replace(SPECS[cfg])
+    if p_override is not None:
+        spec.p = p_override
+    geom = make_geometry(cfg, spec.n, spec.l, spec.bmax, spec.s_lo, spec.s_hi)
+    out = make_pixels(spec, geom, p0, p1, with_meta=with_meta)
+    return (spec, geom) + tuple(out)
+
+
+def xtrue(spec: Spec, geom: Geometry, meta) -> np.ndarray:
+    """On-grid true profile (configuration 5): X_true[p, idx] = amplitude."""
+    p = meta["amp"].shape[0]
+    X = np.zeros((p, geom.l), np.complex128)
+    for slot in range(2):
+        np.add.at(X, (np.arange(p), meta["xtrue_idx"][:, slot]), meta["amp"][:, slot])
+    return X
+
+
+# ------------------------------------------------------------ batched stacks
+
+@dataclasses.dataclass
+class StackSpec:
+    stack: int
+    n: int
+    l: int
+    p: int
+
+
+def batched_specs(num_stacks: int = 64, scale: float = 1.0) -> list[StackSpec]:
+    """Uneven stacks: N ~ U{10..100}, L ~ U{64..1024}, P log-uniform in [1e3, 2.56e5].
+
+    ``scale`` multiplies every pixel count (for reduced test sizes)."""
+    g = _gen(3, 0, 2, 0)
+    out = []
+    for i in range(num_stacks):
+        n = int(g.integers(10, 101))
+        l = int(g.integers(64, 1025))
+        p = int(round(math.exp(g.uniform(math.log(1e3), math.log(2.56e5)))))
+        out.append(StackSpec(i, n, l, max(1, int(round(p * scale)))))
+    return out
+
+
+def make_batched_stack(ss: StackSpec, p0: int = 0, p1: int | None = None):
+    spec = Spec(3, ss.n, ss.l, ss.p, 250.0, -50.0, 50.0, "c1", 10.0)
+    geom = make_geometry(3, ss.n, ss.l, 250.0, -50.0, 50.0, stack=ss.stack + 1)
+    B, lam = make_pixels(spec, geom, p0, p1, stack=ss.stack + 1)
+    return spec, geom, B, lam
+
+
+def to_device_dtypes(A, B, lam):
+    """Round once to the GPU's storage types (complex64 / float32)."""
+    return (np.ascontiguousarray(A, np.complex64), np.ascontiguousarray(B, np.complex64),
+            np.ascontiguousarray(lam, np.float32))
