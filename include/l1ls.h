@@ -1,0 +1,196 @@
+/*
+ * l1ls.h -- C ABI of the MI355X (gfx950) solver for the complex L1-regularised
+ * least-squares problem (basis pursuit denoising) used for super-resolving
+ * tomographic SAR in Shi, Zhu, Yin, Bamler, arXiv 1805.01759.
+ *
+ * Per pixel p the library solves Eq. (1) = Eq. (6) of the paper (no factor 1/2):
+ *     min_x  ||A x - b_p||_2^2 + lambda_p ||x||_1 ,   x in C^L,
+ * where A (N x L) is the irregular Fourier matrix of the TomoSAR imaging model,
+ * Eq. (5): A[n, l] = exp(-j 2 pi xi_n s_l), xi_n = 2 b_n / (lambda_w r).
+ * The solver is Algorithm 1 of the paper (RBPG with backtracking) with a
+ * single block (J = 1): Nesterov extrapolation Eqs. (11)-(12), complex soft
+ * thresholding Eq. (10), the backtracking condition Eq. (15) and the monotone
+ * acceptance test of the algorithm, followed by an optional FP64 refinement on
+ * the support and an FP64 check of the optimality conditions.
+ *
+ * Conventions shared by every entry point
+ *  - Complex values are l1ls_c32 (interleaved float re, im; the layout of
+ *    torch.complex64 / numpy.complex64).
+ *  - A is row-major: A[n * L + l].  B is pixel-major: B[p * N + n].
+ *    X is pixel-major: X[p * L + l].
+ *  - Every pointer named "device" is a HIP device pointer; the caller owns the
+ *    memory.  The library allocates no device memory in any entry point below:
+ *    scratch lives in the caller's workspace.  Work is queued on the given
+ *    stream and nothing synchronises the host.
+ *  - Argument errors are detected on the host before any launch: the call
+ *    returns a negative l1ls_status and l1ls_last_error() describes it.
+ *  - Numerical outcomes are not errors: per-pixel results are reported in
+ *    l1ls_diag.status and the call returns L1LS_OK.
+ *  - Supported sizes: 1 <= N <= 128, 1 <= L <= 1024, 0 <= P < 2^31.
+ */
+#ifndef L1LS_H
+#define L1LS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } l1ls_c32;
+
+typedef enum {
+    L1LS_OK = 0,
+    L1LS_ERR_INVALID_ARG = -1,
+    L1LS_ERR_UNSUPPORTED_SHAPE = -2,
+    L1LS_ERR_WORKSPACE = -3,
+    L1LS_ERR_HIP = -4,
+    L1LS_ERR_INTERNAL = -5
+} l1ls_status;
+
+/* Arithmetic of the two contractions A x and A^H r (the gradient of Eq. (9)).
+ * L1LS_FP32: FP32 MFMA.  L1LS_SPLIT_BF16: every operand split into hi + lo
+ * bfloat16 parts, three MFMA passes (hi*hi + hi*lo + lo*hi) with FP32
+ * accumulation.  Everything else (prox, step, reductions) is FP32; the
+ * refinement and the final optimality check are FP64. */
+typedef enum { L1LS_FP32 = 0, L1LS_SPLIT_BF16 = 1 } l1ls_precision;
+
+/* Per-pixel status bits (diag.status). */
+enum {
+    L1LS_PX_CONVERGED = 1,   /* FP64 KKT residual <= tol at the returned x        */
+    L1LS_PX_MAX_ITER = 2,    /* iteration budget spent before the FP32 test passed */
+    L1LS_PX_NONFINITE = 4,   /* NaN/Inf met in the data or the iteration           */
+    L1LS_PX_POLISHED = 8,    /* FP64 refinement on the support was applied         */
+    L1LS_PX_ZERO = 16,       /* returned x is exactly 0                            */
+    L1LS_PX_BAD_LAMBDA = 32  /* lambda_p <= 0 or not finite: x = 0 returned        */
+};
+
+typedef struct {
+    int32_t max_iter;      /* cap on iterations of Algorithm 1 (N_K); >= 0, default 500      */
+    float tol;             /* KKT residual target (> 0), default 1e-4                          */
+    float c_alpha;         /* backtracking factor C_alpha of Eq. (15), in (0,1); default 0.5   */
+    int32_t precision;     /* l1ls_precision, default L1LS_FP32                                */
+    int32_t backtracking;  /* 1: Eq. (15) line search; 0: fixed step 1/L_f                     */
+    int32_t monotone;      /* 1: accept x-bar only if F(x-bar) <= F(x^k) (Algorithm 1)         */
+    int32_t fp64_polish;   /* 1: FP64 active-set Newton refinement of pixels not yet solved    */
+    int32_t polish_after;  /* hand a pixel to the refinement after this many iterations
+                              (<= max_iter; <= 0 means max_iter)                              */
+    int32_t warm_start;    /* reserved, must be 0                                              */
+} l1ls_options;
+
+/* Device arrays of length P; any may be NULL.
+ *  iters      iterations of Algorithm 1 performed
+ *  kkt        KKT residual of the returned x, evaluated in FP64:
+ *             KKT(x) = L_f max_l |x_l - S_{lambda/L_f}(x_l - g_l/L_f)| / lambda,
+ *             g = 2 A^H (A x - b), L_f = 2 lambda_max(A A^H)
+ *  objective  F(x) = ||Ax - b||^2 + lambda ||x||_1 (FP64-evaluated, stored FP32)
+ *  status     L1LS_PX_* bits
+ *  nnz        number of nonzero entries of x */
+typedef struct {
+    int32_t *iters;
+    float *kkt;
+    float *objective;
+    uint32_t *status;
+    int32_t *nnz;
+} l1ls_diag;
+
+/* Defaults: max_iter 500, tol 1e-4, c_alpha 0.5, FP32, backtracking, monotone,
+ * FP64 polish after max_iter. */
+l1ls_options l1ls_options_default(void);
+
+/* Bytes of device workspace l1ls_solve needs for these sizes and options. */
+l1ls_status l1ls_workspace_size(int32_t n, int32_t l, int64_t p, const l1ls_options *opt,
+                                size_t *bytes);
+
+/* Solve Eq. (1) for every pixel of one stack.
+ *  A        device, n*l, row-major, shared by all pixels
+ *  B        device, p*n, pixel-major measurement vectors g_p of Eq. (5)
+ *  lambda   device float; lambda_stride 0 = one value for all pixels, else
+ *           lambda[p * lambda_stride]
+ *  X        device, p*l: output (the pixel's x)
+ *  diag     host struct of device pointers (may be NULL)
+ *  workspace/ws_bytes  device scratch of at least l1ls_workspace_size bytes,
+ *           16-byte aligned; its contents on entry are ignored
+ * Returns L1LS_OK, or a negative status with no work queued.  p = 0 is a no-op. */
+l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                       const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                       l1ls_c32 *X, const l1ls_diag *diag, void *workspace, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched stacks of uneven size (each with its own A, N, L and pixel count) in
+ * one persistent launch per shape class.  The plan holds host tables and the
+ * tile shape chosen for each stack; execute only launches kernels (no
+ * allocation, no host synchronisation, no branching on device data), so it may
+ * be captured into a HIP graph.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n, l;
+    int64_t p;
+    const l1ls_c32 *A;       /* device */
+    const l1ls_c32 *B;       /* device */
+    const float *lambda;     /* device */
+    int64_t lambda_stride;
+    l1ls_c32 *X;             /* device */
+    l1ls_diag diag;
+} l1ls_stack;
+
+typedef struct l1ls_plan l1ls_plan;
+
+/* Build a plan from the shapes (n, l, p) of `stacks` (their pointers are not
+ * read).  The options are copied into the plan. */
+l1ls_status l1ls_plan_create(const l1ls_stack *stacks, int32_t count, const l1ls_options *opt,
+                             l1ls_plan **out);
+l1ls_status l1ls_plan_workspace_size(const l1ls_plan *plan, size_t *bytes);
+/* `stacks` must have the shapes given at plan creation. */
+l1ls_status l1ls_plan_execute(l1ls_plan *plan, const l1ls_stack *stacks, void *workspace,
+                              size_t ws_bytes, hipStream_t stream);
+void l1ls_plan_destroy(l1ls_plan *plan);
+/* Describe the plan (tile class per stack) into buf; returns chars needed. */
+int32_t l1ls_plan_describe(const l1ls_plan *plan, char *buf, int32_t buf_len);
+
+/* ---------------------------------------------------------------------------
+ * Unrolled fixed-step map and its adjoint (differentiation through K
+ * iterations of Eqs. (11)-(12) with constant step alpha, no backtracking and no
+ * monotone test).  A is built on the device from xi (N) and the elevation grid
+ * s (L) as exp(-j 2 pi xi_n s_l).
+ *
+ * forward: X_K from x^0 = x^{-1} = 0.  tape (device, tape_bytes >=
+ *   l1ls_unrolled_tape_size) receives checkpoints (x^k, x^{k-1}) every
+ *   ckpt_every iterations for the backward pass.
+ * backward: given dX = dloss/dX_K (complex, dRe + j dIm), writes
+ *   dB (p*n complex), dlambda (1 float, device) and dxi (n floats, device).
+ *   ws (device) >= l1ls_unrolled_backward_ws_size bytes.
+ * ------------------------------------------------------------------------- */
+l1ls_status l1ls_unrolled_tape_size(int32_t n, int32_t l, int64_t p, int32_t K,
+                                    int32_t ckpt_every, size_t *bytes);
+l1ls_status l1ls_unrolled_backward_ws_size(int32_t n, int32_t l, int64_t p, int32_t K,
+                                           int32_t ckpt_every, size_t *bytes);
+l1ls_status l1ls_unrolled_forward(int32_t n, int32_t l, int64_t p, const float *xi,
+                                  const float *s, const l1ls_c32 *B, float lambda, float alpha,
+                                  int32_t K, int32_t ckpt_every, l1ls_c32 *X_K, void *tape,
+                                  size_t tape_bytes, hipStream_t stream);
+l1ls_status l1ls_unrolled_backward(int32_t n, int32_t l, int64_t p, const float *xi,
+                                   const float *s, const l1ls_c32 *B, float lambda, float alpha,
+                                   int32_t K, int32_t ckpt_every, const void *tape,
+                                   size_t tape_bytes, const l1ls_c32 *dX, l1ls_c32 *dB,
+                                   float *dlambda, float *dxi, void *ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/* Name of a status code; detail of the last error on the calling thread. */
+const char *l1ls_status_string(l1ls_status s);
+const char *l1ls_last_error(void);
+
+/* Average duration in milliseconds of the main iteration kernel over the
+ * launches made since the last reset, measured with HIP events on the stream
+ * it was launched on (only when timing is enabled). */
+void l1ls_timing_enable(int32_t on);
+int32_t l1ls_timing_read(double *total_ms, int32_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

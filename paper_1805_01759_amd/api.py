@@ -1,0 +1,125 @@
+"""PyTorch-facing calls of the gfx950 L1LS solver (marshalling only).
+
+Every step of the solve runs in the HIP kernels of libl1ls.so; PyTorch only
+provides device memory and the stream.  If the library is missing this module
+raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracking=True,
+            monotone=True, fp64_polish=True, polish_after=0) -> _lib.Options:
+    o = _lib.load().l1ls_options_default()
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.c_alpha = float(c_alpha)
+    o.precision = {"fp32": _lib.L1LS_FP32, "split_bf16": _lib.L1LS_SPLIT_BF16}[precision]
+    o.backtracking = int(bool(backtracking))
+    o.monotone = int(bool(monotone))
+    o.fp64_polish = int(bool(fp64_polish))
+    o.polish_after = int(polish_after)
+    return o
+
+
+def _check_inputs(A, B, lam):
+    if A.dtype != torch.complex64 or B.dtype != torch.complex64:
+        raise TypeError("A and B must be complex64")
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("A and B must be device tensors")
+    if A.dim() != 2 or B.dim() != 2 or B.shape[1] != A.shape[0]:
+        raise ValueError(f"shapes: A (N, L), B (P, N); got {tuple(A.shape)}, {tuple(B.shape)}")
+    A = A.contiguous()
+    B = B.contiguous()
+    p = B.shape[0]
+    if isinstance(lam, torch.Tensor):
+        lam_t = lam.to(device=B.device, dtype=torch.float32).contiguous().reshape(-1)
+    else:
+        lam_t = torch.tensor([float(lam)], device=B.device, dtype=torch.float32)
+    if lam_t.numel() == 1:
+        stride = 0
+    elif lam_t.numel() == p:
+        stride = 1
+    else:
+        raise ValueError("lambda must be a scalar or have one value per pixel")
+    return A, B, lam_t, stride
+
+
+class Workspace:
+    """A reusable device byte buffer (grown on demand, 256-byte aligned)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        return self.buf[off:off + nbytes]
+
+
+_default_ws = Workspace()
+
+
+def workspace_size(n: int, l: int, p: int, opts: _lib.Options | None = None) -> int:
+    L = _lib.load()
+    sz = ctypes.c_size_t(0)
+    _lib.check(L.l1ls_workspace_size(n, l, p, ctypes.byref(opts) if opts else None,
+                                     ctypes.byref(sz)), "l1ls_workspace_size")
+    return sz.value
+
+
+def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = None,
+          workspace: Workspace | None = None, stream=None, **opts):
+    """Solve min ||A x - b_p||^2 + lambda_p ||x||_1 for every row b_p of B.
+
+    Returns (X, diag) with X (P, L) complex64 and diag a dict of device tensors
+    (iters int32, kkt float32, objective float32, status int32 bits, nnz int32).
+    """
+    L = _lib.load()
+    A, B, lam_t, stride = _check_inputs(A, B, lam)
+    n, l = A.shape
+    p = B.shape[0]
+    o = options(**opts)
+    X = out if out is not None else torch.empty((p, l), dtype=torch.complex64, device=B.device)
+    diag = {
+        "iters": torch.empty(p, dtype=torch.int32, device=B.device),
+        "kkt": torch.empty(p, dtype=torch.float32, device=B.device),
+        "objective": torch.empty(p, dtype=torch.float32, device=B.device),
+        "status": torch.empty(p, dtype=torch.int32, device=B.device),
+        "nnz": torch.empty(p, dtype=torch.int32, device=B.device),
+    }
+    d = _lib.Diag(diag["iters"].data_ptr(), diag["kkt"].data_ptr(), diag["objective"].data_ptr(),
+                  diag["status"].data_ptr(), diag["nnz"].data_ptr())
+    ws = (workspace or _default_ws).get(workspace_size(n, l, p, o), B.device)
+    _lib.check(L.l1ls_solve(n, l, p, _ptr(A), _ptr(B), _ptr(lam_t), stride, ctypes.byref(o),
+                            _ptr(X), ctypes.byref(d), _ptr(ws), ws.numel(), _stream(stream)),
+               "l1ls_solve")
+    return X, diag
+
+
+def timing_enable(on: bool = True) -> None:
+    _lib.load().l1ls_timing_enable(int(on))
+
+
+def timing_read():
+    """(total milliseconds, launches) of the iteration kernel since the last read."""
+    tot = ctypes.c_double(0.0)
+    cnt = ctypes.c_int32(0)
+    _lib.load().l1ls_timing_read(ctypes.byref(tot), ctypes.byref(cnt))
+    return tot.value, cnt.value

@@ -1,0 +1,343 @@
+// C ABI of the gfx950 L1LS solver: argument validation, workspace layout and
+// the launch sequence (setup -> persistent iteration -> FP64 refinement ->
+// FP64 optimality check).  All work is queued on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "l1ls_internal.h"
+
+namespace l1ls {
+
+static thread_local char g_err[512];
+
+static l1ls_status fail(l1ls_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int slice_blocks_for(int l) { return l <= 256 ? 8 : 16; }
+int waves_for(int l)
+{
+    const int slice = 8 * slice_blocks_for(l);
+    return (l + slice - 1) / slice;
+}
+int lpad_for(int l) { return waves_for(l) * 8 * slice_blocks_for(l); }
+int zblocks_for(int n) { return (2 * n + 15) / 16; }
+
+StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
+{
+    StackWorkspace w;
+    const int l_pad = lpad_for(l);
+    size_t off = 0;
+    w.a_packed = off;
+    off = align_up(off + (size_t)n * l_pad * sizeof(float2), 256);
+    w.gram = off;
+    off = align_up(off + (size_t)n * n * sizeof(double2), 256);
+    w.consts = off;
+    off = align_up(off + sizeof(StackConsts), 256);
+    w.queue = off;
+    off = align_up(off + 4 * sizeof(uint32_t), 256);
+    w.status = off;
+    off = align_up(off + (size_t)p * sizeof(uint32_t), 256);
+    w.iters = off;
+    off = align_up(off + (size_t)p * sizeof(int32_t), 256);
+    w.kkt32 = off;
+    off = align_up(off + (size_t)p * sizeof(float), 256);
+    w.polish_list = off;
+    off = align_up(off + (size_t)p * sizeof(int32_t), 256);
+    w.total = off;
+    return w;
+}
+
+// Largest supported shapes of the persistent kernel.
+constexpr int kMaxNSolve = 64;    // 2N <= 8 MFMA row blocks
+constexpr int kMaxLSolve = 512;   // 8 waves of 64 unknowns
+
+static l1ls_status check_options(const l1ls_options *o)
+{
+    if (!o) return fail(L1LS_ERR_INVALID_ARG, "options pointer is NULL");
+    if (o->max_iter < 0) return fail(L1LS_ERR_INVALID_ARG, "max_iter must be >= 0 (got %d)", o->max_iter);
+    if (!(o->tol > 0.0f) || !isfinite(o->tol))
+        return fail(L1LS_ERR_INVALID_ARG, "tol must be finite and > 0");
+    if (!(o->c_alpha > 0.0f && o->c_alpha < 1.0f))
+        return fail(L1LS_ERR_INVALID_ARG, "c_alpha must lie in (0, 1)");
+    if (o->precision != L1LS_FP32 && o->precision != L1LS_SPLIT_BF16)
+        return fail(L1LS_ERR_INVALID_ARG, "unknown precision %d", o->precision);
+    if (o->warm_start != 0) return fail(L1LS_ERR_INVALID_ARG, "warm_start is not supported");
+    return L1LS_OK;
+}
+
+static l1ls_status check_shape(int32_t n, int32_t l, int64_t p)
+{
+    if (n < 1 || l < 1 || p < 0) return fail(L1LS_ERR_INVALID_ARG, "need n >= 1, l >= 1, p >= 0");
+    if (p >= ((int64_t)1 << 31)) return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "p must be < 2^31");
+    if (n > kMaxNSolve || l > kMaxLSolve)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "supported sizes: n <= %d, l <= %d (got %d, %d)",
+                    kMaxNSolve, kMaxLSolve, n, l);
+    return L1LS_OK;
+}
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Event timing of the persistent kernel (opt-in, for measurement).
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+
+struct TimedLaunch {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t s;
+    explicit TimedLaunch(hipStream_t st) : s(st)
+    {
+        std::lock_guard<std::mutex> g(g_tmu);
+        if (!g_timing) return;
+        hipEventCreate(&e0);
+        hipEventCreate(&e1);
+        hipEventRecord(e0, s);
+    }
+    ~TimedLaunch()
+    {
+        if (!e0) return;
+        hipEventRecord(e1, s);
+        std::lock_guard<std::mutex> g(g_tmu);
+        g_events.push_back({e0, e1});
+    }
+};
+
+static l1ls_status solve_impl(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                              const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                              l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
+                              hipStream_t s)
+{
+    l1ls_status st = check_shape(n, l, p);
+    if (st != L1LS_OK) return st;
+    st = check_options(opt);
+    if (st != L1LS_OK) return st;
+    if (p == 0) return L1LS_OK;
+    if (!A || !B || !lambda || !X || !ws) return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
+    if (!aligned(A, 8) || !aligned(B, 8) || !aligned(X, 8) || !aligned(lambda, 4))
+        return fail(L1LS_ERR_INVALID_ARG, "A, B, X must be 8-byte aligned and lambda 4-byte aligned");
+    if (!aligned(ws, 256)) return fail(L1LS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (lambda_stride < 0) return fail(L1LS_ERR_INVALID_ARG, "lambda_stride must be >= 0");
+    const StackWorkspace lay = stack_workspace_layout(n, l, p);
+    if (ws_bytes < lay.total)
+        return fail(L1LS_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
+
+    char *w = (char *)ws;
+    const int waves = waves_for(l), l_pad = lpad_for(l);
+    float2 *Ap = (float2 *)(w + lay.a_packed);
+    double2 *gram = (double2 *)(w + lay.gram);
+    StackConsts *consts = (StackConsts *)(w + lay.consts);
+    uint32_t *queue = (uint32_t *)(w + lay.queue);
+    uint32_t *status_ws = (uint32_t *)(w + lay.status);
+    int32_t *iters_ws = (int32_t *)(w + lay.iters);
+    float *kkt32 = (float *)(w + lay.kkt32);
+    int32_t *plist = (int32_t *)(w + lay.polish_list);
+
+    hipError_t e = launch_setup(n, l, l_pad, (const float2 *)A, Ap, gram, consts, queue, s);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "setup launch: %s", hipGetErrorString(e));
+
+    FistaArgs fa;
+    fa.n = n;
+    fa.l = l;
+    fa.l_pad = l_pad;
+    fa.waves = waves;
+    fa.p = p;
+    fa.A = Ap;
+    fa.B = (const float2 *)B;
+    fa.lambda = lambda;
+    fa.lambda_stride = lambda_stride;
+    fa.X = (float2 *)X;
+    fa.iters = iters_ws;
+    fa.kkt32 = kkt32;
+    fa.status = status_ws;
+    fa.consts = consts;
+    fa.queue = queue;
+    fa.polish_count = queue + 1;
+    fa.polish_list = plist;
+    int cap = opt->max_iter;
+    if (opt->polish_after > 0 && opt->polish_after < cap) cap = opt->polish_after;
+    fa.fista_cap = cap;
+    fa.tol = opt->tol;
+    fa.c_alpha = opt->c_alpha;
+    fa.backtracking = opt->backtracking ? 1 : 0;
+    fa.monotone = opt->monotone ? 1 : 0;
+    fa.polish = opt->fp64_polish ? 1 : 0;
+    {
+        TimedLaunch t(s);
+        e = launch_fista(fa, opt->precision, 0, s);
+    }
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
+
+    CertifyArgs ca;
+    ca.n = n;
+    ca.l = l;
+    ca.l_pad = l_pad;
+    ca.p = p;
+    ca.A = Ap;
+    ca.B = (const float2 *)B;
+    ca.lambda = lambda;
+    ca.lambda_stride = lambda_stride;
+    ca.X = (float2 *)X;
+    ca.iters_in = iters_ws;
+    ca.status_in = status_ws;
+    ca.consts = consts;
+    ca.tol = opt->tol;
+    ca.polish = opt->fp64_polish;
+    ca.iters = diag ? diag->iters : nullptr;
+    ca.kkt = diag ? diag->kkt : nullptr;
+    ca.objective = diag ? diag->objective : nullptr;
+    ca.status = diag ? diag->status : nullptr;
+    ca.nnz = diag ? diag->nnz : nullptr;
+    e = launch_certify(ca, s);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "certify launch: %s", hipGetErrorString(e));
+    return L1LS_OK;
+}
+
+}  // namespace l1ls
+
+using namespace l1ls;
+
+extern "C" {
+
+l1ls_options l1ls_options_default(void)
+{
+    l1ls_options o;
+    o.max_iter = 500;
+    o.tol = 1e-4f;
+    o.c_alpha = 0.5f;
+    o.precision = L1LS_FP32;
+    o.backtracking = 1;
+    o.monotone = 1;
+    o.fp64_polish = 1;
+    o.polish_after = 0;
+    o.warm_start = 0;
+    return o;
+}
+
+l1ls_status l1ls_workspace_size(int32_t n, int32_t l, int64_t p, const l1ls_options *opt,
+                                size_t *bytes)
+{
+    if (!bytes) return fail(L1LS_ERR_INVALID_ARG, "bytes pointer is NULL");
+    l1ls_status st = check_shape(n, l, p);
+    if (st != L1LS_OK) return st;
+    if (opt) {
+        st = check_options(opt);
+        if (st != L1LS_OK) return st;
+    }
+    *bytes = stack_workspace_layout(n, l, p).total;
+    return L1LS_OK;
+}
+
+l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                       const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                       l1ls_c32 *X, const l1ls_diag *diag, void *workspace, size_t ws_bytes,
+                       hipStream_t stream)
+{
+    return solve_impl(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, workspace, ws_bytes,
+                      stream);
+}
+
+const char *l1ls_status_string(l1ls_status s)
+{
+    switch (s) {
+    case L1LS_OK: return "L1LS_OK";
+    case L1LS_ERR_INVALID_ARG: return "L1LS_ERR_INVALID_ARG";
+    case L1LS_ERR_UNSUPPORTED_SHAPE: return "L1LS_ERR_UNSUPPORTED_SHAPE";
+    case L1LS_ERR_WORKSPACE: return "L1LS_ERR_WORKSPACE";
+    case L1LS_ERR_HIP: return "L1LS_ERR_HIP";
+    case L1LS_ERR_INTERNAL: return "L1LS_ERR_INTERNAL";
+    }
+    return "unknown status";
+}
+
+const char *l1ls_last_error(void) { return g_err; }
+
+void l1ls_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_timing = on != 0;
+}
+
+int32_t l1ls_timing_read(double *total_ms, int32_t *launches)
+{
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> g(g_tmu);
+        ev.swap(g_events);
+    }
+    double tot = 0.0;
+    int cnt = 0;
+    for (auto &pr : ev) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(pr.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+            tot += ms;
+            ++cnt;
+        }
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
+    return cnt;
+}
+
+// ---- entry points still to be provided by later kernels
+struct l1ls_plan { int dummy; };
+l1ls_status l1ls_plan_create(const l1ls_stack *, int32_t, const l1ls_options *, l1ls_plan **out)
+{
+    if (out) *out = nullptr;
+    return fail(L1LS_ERR_INTERNAL, "batched plans are not available in this build");
+}
+l1ls_status l1ls_plan_workspace_size(const l1ls_plan *, size_t *bytes)
+{
+    if (bytes) *bytes = 0;
+    return fail(L1LS_ERR_INTERNAL, "batched plans are not available in this build");
+}
+l1ls_status l1ls_plan_execute(l1ls_plan *, const l1ls_stack *, void *, size_t, hipStream_t)
+{
+    return fail(L1LS_ERR_INTERNAL, "batched plans are not available in this build");
+}
+void l1ls_plan_destroy(l1ls_plan *) {}
+int32_t l1ls_plan_describe(const l1ls_plan *, char *buf, int32_t n)
+{
+    if (buf && n > 0) buf[0] = 0;
+    return 0;
+}
+l1ls_status l1ls_unrolled_tape_size(int32_t, int32_t, int64_t, int32_t, int32_t, size_t *bytes)
+{
+    if (bytes) *bytes = 0;
+    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+}
+l1ls_status l1ls_unrolled_backward_ws_size(int32_t, int32_t, int64_t, int32_t, int32_t, size_t *bytes)
+{
+    if (bytes) *bytes = 0;
+    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+}
+l1ls_status l1ls_unrolled_forward(int32_t, int32_t, int64_t, const float *, const float *,
+                                  const l1ls_c32 *, float, float, int32_t, int32_t, l1ls_c32 *,
+                                  void *, size_t, hipStream_t)
+{
+    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+}
+l1ls_status l1ls_unrolled_backward(int32_t, int32_t, int64_t, const float *, const float *,
+                                   const l1ls_c32 *, float, float, int32_t, int32_t, const void *,
+                                   size_t, const l1ls_c32 *, l1ls_c32 *, float *, float *, void *,
+                                   size_t, hipStream_t)
+{
+    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+}
+
+}  // extern "C"

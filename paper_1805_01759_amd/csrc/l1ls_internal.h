@@ -1,0 +1,88 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernels of the
+// gfx950 solver.  Not part of the public interface (include/l1ls.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/l1ls.h"
+
+namespace l1ls {
+
+// A wave owns 8 KB complex unknowns of every pixel in its tile (KB MFMA row
+// blocks of 16 real rows, KB = 8 for L <= 256, 16 for L <= 512); a workgroup
+// of W <= 4 waves (one per SIMD) covers L <= 8 KB W.
+constexpr int kTile = 16;        // pixels per workgroup (MFMA N dimension)
+constexpr int kMaxWavesIter = 4;
+constexpr int kMaxWaves = 16;    // staging bound: L <= 1024
+constexpr int kMaxN = 128;
+constexpr int kMaxZB = 16;       // ceil(2 N / 16) <= 16
+
+// Device-side per-stack constants written by the setup kernel.
+struct StackConsts {
+    double lf;       // 2 lambda_max(A A^H)
+    double alpha0;   // 1 / (2 max_l ||a_l||^2)
+    double lmax_it;  // power iterations used (diagnostic)
+    double pad;
+};
+
+struct FistaArgs {
+    int n, l, l_pad, waves;
+    int64_t p;
+    const float2 *A;          // packed: n x l_pad, zero padded columns
+    const float2 *B;          // p x n
+    const float *lambda;
+    int64_t lambda_stride;
+    float2 *X;                // p x l
+    int32_t *iters;
+    float *kkt32;             // FP32 KKT at exit of the iteration (workspace)
+    uint32_t *status;         // workspace status (always present)
+    const StackConsts *consts;
+    uint32_t *queue;          // [0] next pixel
+    uint32_t *polish_count;   // number of pixels appended to polish_list
+    int32_t *polish_list;
+    int32_t fista_cap;        // retire unsolved pixels after this many iterations
+    float tol, c_alpha;
+    int32_t backtracking, monotone, polish;
+};
+
+struct CertifyArgs {
+    int n, l, l_pad;
+    int64_t p;
+    const float2 *A;          // packed n x l_pad
+    const float2 *B;
+    const float *lambda;
+    int64_t lambda_stride;
+    float2 *X;
+    const int32_t *iters_in;
+    const uint32_t *status_in;
+    const StackConsts *consts;
+    float tol;
+    int32_t polish;           // 1: refine pixels above tol
+    // outputs (any may be null)
+    int32_t *iters;
+    float *kkt;
+    float *objective;
+    uint32_t *status;
+    int32_t *nnz;
+};
+
+// Workspace layout for one stack.
+struct StackWorkspace {
+    size_t a_packed, consts, queue, status, iters, kkt32, polish_list, gram, total;
+};
+StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
+
+int slice_blocks_for(int l);   // KB
+int waves_for(int l);          // W
+int lpad_for(int l);           // 8 KB W
+int zblocks_for(int n);
+
+hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, double2 *gram,
+                        StackConsts *consts, uint32_t *queue, hipStream_t s);
+hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s);
+hipError_t launch_certify(const CertifyArgs &a, hipStream_t s);
+size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds);
+bool fista_a_fits_lds(int n, int l_pad, int waves, int zb);
+
+}  // namespace l1ls
