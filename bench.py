@@ -1,0 +1,156 @@
+#!/usr/bin/env python
+"""Throughput of the gfx950 L1LS solver: pixels solved per second at KKT <= 1e-4.
+
+One step = one full solve (setup, accelerated proximal-gradient iteration,
+FP64 refinement, FP64 optimality check) of a synthetic scene-scale TomoSAR
+stack already resident in HBM: N = 25 acquisitions, L = 256 elevation bins,
+P = 2^20 pixels, max 500 iterations, tol 1e-4.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "pixels solved/sec at KKT residual ≤1e-4 (FP32 vs split-BF16); MFMA %"
+PEAK = {"fp32": 157.3e12, "split_bf16": 2.5e15}
+WORKLOADS = {
+    # name: (synth config id, description)
+    "scene": (2, "scene-scale TomoSAR stack: N=25, L=256, P=1048576, baselines U[-300,300] m, "
+                 "0/1/2 scatterers (0.3/0.5/0.2), SNR U[0,20] dB, lambda_p = sigma_p sqrt(2 N ln L)"),
+    "tiny": (1, "tiny TomoSAR stack: N=15, L=101, P=1024, SNR 10 dB"),
+}
+
+
+def kernel_sha() -> str:
+    src = os.path.join(HERE, "paper_1805_01759_amd", "csrc", "fista.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    path = os.path.join(HERE, "profiles", f"fista_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha") != kernel_sha():
+        return None  # counters were taken on a different kernel
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(A, B, lam, sample: int, max_iter: int, tol: float):
+    import oracle  # CPU oracle: timed beside the GPU, never on the product path
+    oracle.build(force=False)
+    nthreads = oracle.default_threads()
+    t0 = time.perf_counter()
+    X, d = oracle.rbpg_batch(A[:, :].astype(np.complex128), B[:sample].astype(np.complex128),
+                             lam[:sample].astype(np.float64), tol=tol, max_iter=max_iter,
+                             nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    solved = int(d["converged"].sum())
+    return {"value": solved / dt, "unit": "pixels/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"first {sample} pixels of the same stack; Algorithm 1 (J=1) in FP64, "
+                      f"tol {tol}, max {max_iter} iterations; {solved} solved in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="scene", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
+    ap.add_argument("--max-iter", type=int, default=500)
+    ap.add_argument("--polish-after", type=int, default=200)
+    ap.add_argument("--polish", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver has no multi-GPU path (pixels are "
+              "independent; see the sharding note in DESIGN.md). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
+    from paper_1805_01759_amd import api, synth
+
+    cfg, desc = WORKLOADS[args.workload]
+    spec, geom, B, lam = synth.make_config(cfg)
+    A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
+    dev = torch.device("cuda:0")
+    Ad = torch.from_numpy(A32).to(dev)
+    Bd = torch.from_numpy(B32).to(dev)
+    ld = torch.from_numpy(l32).to(dev)
+    n, l = A32.shape
+    p = B32.shape[0]
+    opts = dict(max_iter=args.max_iter, tol=1e-4, precision=args.precision,
+                fp64_polish=args.polish, polish_after=args.polish_after)
+    X = torch.empty((p, l), dtype=torch.complex64, device=dev)
+    ws = api.Workspace()
+    for _ in range(args.warmup):
+        api.solve(Ad, Bd, ld, out=X, workspace=ws, **opts)
+    torch.cuda.synchronize()
+    api.timing_enable(True)
+    api.timing_read()
+    diags = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, d = api.solve(Ad, Bd, ld, out=X, workspace=ws, **opts)
+        diags.append(d["status"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_launches = api.timing_read()
+    api.timing_enable(False)
+    solved = sum(int(((s & 1) != 0).sum().item()) for s in diags)
+    fwd, adj, npol = api.solve_counters(n, l, p, d)
+    flops = (fwd + adj) * 8.0 * n * l          # algorithmic flops of one iteration launch
+    k_avg_s = (k_ms / max(k_launches, 1)) / 1e3
+    achieved = flops / k_avg_s
+    traffic = load_traffic(args.workload)
+    rec = {
+        "metric": METRIC,
+        "value": solved / dt,
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "l": l, "pixels": p, "max_iter": args.max_iter,
+                   "tol": 1e-4, "precision": args.precision, "polish_after": args.polish_after,
+                   "solved_fraction": solved / (p * args.steps), "pixels_refined_fp64": npol},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
+                     "traffic": traffic, "kernel": "fista_kernel",
+                     "kernel_ms": k_avg_s * 1e3,
+                     "flops_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(A32, B32, l32, min(args.cpu_sample, p), args.max_iter, 1e-4)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

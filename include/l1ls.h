@@ -75,7 +75,8 @@ typedef struct {
     int32_t precision;     /* l1ls_precision, default L1LS_FP32                                */
     int32_t backtracking;  /* 1: Eq. (15) line search; 0: fixed step 1/L_f                     */
     int32_t monotone;      /* 1: accept x-bar only if F(x-bar) <= F(x^k) (Algorithm 1)         */
-    int32_t fp64_polish;   /* 1: FP64 active-set Newton refinement of pixels not yet solved    */
+    int32_t fp64_polish;   /* FP64 active-set Newton refinement: 0 off; 1 pixels whose FP64
+                              KKT residual exceeds tol; 2 every pixel (to FP64 precision)      */
     int32_t polish_after;  /* hand a pixel to the refinement after this many iterations
                               (<= max_iter; <= 0 means max_iter)                              */
     int32_t warm_start;    /* reserved, must be 0                                              */
@@ -179,6 +180,12 @@ l1ls_status l1ls_unrolled_backward(int32_t n, int32_t l, int64_t p, const float 
                                    size_t tape_bytes, const l1ls_c32 *dX, l1ls_c32 *dB,
                                    float *dlambda, float *dxi, void *ws, size_t ws_bytes,
                                    hipStream_t stream);
+
+/* Work counters of the last l1ls_solve that used `workspace` (synchronises
+ * `stream`): out[0] pixel forward products A d, out[1] pixel adjoint products
+ * A^H r (each 8 N L real flops), out[2] pixels handed to the FP64 refinement. */
+l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *workspace,
+                                hipStream_t stream, uint64_t out[3]);
 
 /* Name of a status code; detail of the last error on the calling thread. */
 const char *l1ls_status_string(l1ls_status s);

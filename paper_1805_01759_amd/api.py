@@ -23,7 +23,7 @@ def _stream(stream=None):
 
 
 def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracking=True,
-            monotone=True, fp64_polish=True, polish_after=0) -> _lib.Options:
+            monotone=True, fp64_polish=1, polish_after=0) -> _lib.Options:
     o = _lib.load().l1ls_options_default()
     o.max_iter = int(max_iter)
     o.tol = float(tol)
@@ -31,7 +31,7 @@ def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracki
     o.precision = {"fp32": _lib.L1LS_FP32, "split_bf16": _lib.L1LS_SPLIT_BF16}[precision]
     o.backtracking = int(bool(backtracking))
     o.monotone = int(bool(monotone))
-    o.fp64_polish = int(bool(fp64_polish))
+    o.fp64_polish = int(fp64_polish)  # 0 off, 1 pixels above tol, 2 every pixel
     o.polish_after = int(polish_after)
     return o
 
@@ -110,7 +110,16 @@ def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = N
     _lib.check(L.l1ls_solve(n, l, p, _ptr(A), _ptr(B), _ptr(lam_t), stride, ctypes.byref(o),
                             _ptr(X), ctypes.byref(d), _ptr(ws), ws.numel(), _stream(stream)),
                "l1ls_solve")
+    diag["_ws"] = ws
     return X, diag
+
+
+def solve_counters(n: int, l: int, p: int, diag, stream=None):
+    """(forward products, adjoint products, pixels refined) of the solve that made `diag`."""
+    out = (ctypes.c_uint64 * 3)()
+    _lib.check(_lib.load().l1ls_solve_counters(n, l, p, _ptr(diag["_ws"]), _stream(stream),
+                                               ctypes.byref(out)), "l1ls_solve_counters")
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def timing_enable(on: bool = True) -> None:

@@ -48,6 +48,8 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     off = align_up(off + sizeof(StackConsts), 256);
     w.queue = off;
     off = align_up(off + 4 * sizeof(uint32_t), 256);
+    w.work = off;
+    off = align_up(off + 2 * sizeof(unsigned long long), 256);
     w.status = off;
     off = align_up(off + (size_t)p * sizeof(uint32_t), 256);
     w.iters = off;
@@ -75,6 +77,8 @@ static l1ls_status check_options(const l1ls_options *o)
     if (o->precision != L1LS_FP32 && o->precision != L1LS_SPLIT_BF16)
         return fail(L1LS_ERR_INVALID_ARG, "unknown precision %d", o->precision);
     if (o->warm_start != 0) return fail(L1LS_ERR_INVALID_ARG, "warm_start is not supported");
+    if (o->fp64_polish < 0 || o->fp64_polish > 2)
+        return fail(L1LS_ERR_INVALID_ARG, "fp64_polish must be 0, 1 or 2");
     return L1LS_OK;
 }
 
@@ -145,7 +149,8 @@ static l1ls_status solve_impl(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A
     float *kkt32 = (float *)(w + lay.kkt32);
     int32_t *plist = (int32_t *)(w + lay.polish_list);
 
-    hipError_t e = launch_setup(n, l, l_pad, (const float2 *)A, Ap, gram, consts, queue, s);
+    unsigned long long *work = (unsigned long long *)(w + lay.work);
+    hipError_t e = launch_setup(n, l, l_pad, (const float2 *)A, Ap, gram, consts, queue, work, s);
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "setup launch: %s", hipGetErrorString(e));
 
     FistaArgs fa;
@@ -166,6 +171,7 @@ static l1ls_status solve_impl(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A
     fa.queue = queue;
     fa.polish_count = queue + 1;
     fa.polish_list = plist;
+    fa.work = work;
     int cap = opt->max_iter;
     if (opt->polish_after > 0 && opt->polish_after < cap) cap = opt->polish_after;
     fa.fista_cap = cap;
@@ -173,12 +179,36 @@ static l1ls_status solve_impl(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A
     fa.c_alpha = opt->c_alpha;
     fa.backtracking = opt->backtracking ? 1 : 0;
     fa.monotone = opt->monotone ? 1 : 0;
-    fa.polish = opt->fp64_polish ? 1 : 0;
+    fa.polish = opt->fp64_polish;
     {
         TimedLaunch t(s);
         e = launch_fista(fa, opt->precision, 0, s);
     }
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
+
+    if (opt->fp64_polish) {
+        PolishArgsDev pa;
+        pa.n = n;
+        pa.l = l;
+        pa.l_pad = l_pad;
+        pa.A = Ap;
+        pa.B = (const float2 *)B;
+        pa.lambda = lambda;
+        pa.lambda_stride = lambda_stride;
+        pa.X = (float2 *)X;
+        pa.consts = consts;
+        pa.count = queue + 1;
+        pa.list = plist;
+        pa.status = status_ws;
+        pa.rounds = 64;
+        pa.mode = opt->fp64_polish;
+        pa.tol = opt->tol;
+        int dev = 0, cus = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        e = launch_polish(pa, cus * 8, s);
+        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "polish launch: %s", hipGetErrorString(e));
+    }
 
     CertifyArgs ca;
     ca.n = n;
@@ -263,6 +293,26 @@ const char *l1ls_status_string(l1ls_status s)
 }
 
 const char *l1ls_last_error(void) { return g_err; }
+
+l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *workspace,
+                                hipStream_t stream, uint64_t out[3])
+{
+    if (!workspace || !out) return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
+    const StackWorkspace lay = stack_workspace_layout(n, l, p);
+    unsigned long long w2[2] = {0, 0};
+    uint32_t q[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(w2, (const char *)workspace + lay.work, sizeof w2,
+                                  hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(q, (const char *)workspace + lay.queue, sizeof q, hipMemcpyDeviceToHost,
+                           stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "counter read: %s", hipGetErrorString(e));
+    out[0] = w2[0];
+    out[1] = w2[1];
+    out[2] = q[1];
+    return L1LS_OK;
+}
 
 void l1ls_timing_enable(int32_t on)
 {

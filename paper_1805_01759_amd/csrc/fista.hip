@@ -232,9 +232,11 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
             for (int r = 0; r < 4; ++r) G[b][r] = acc[b][r];
     };
 
+    unsigned long long n_fwd = 0, n_adj = 0;  // pixel products (wave 0, lane 0 counts)
     refill(0xFFFFu);
     if (__ballot(active) == 0) return;
     adjoint();
+    n_adj += __popcll(__ballot(active && h == 0));
 
     for (;;) {
         const float beta = fmaxf(0.0f, (float)(k - 2) / (float)(k + 1));
@@ -258,6 +260,7 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
         kmax = max_h(kmax);
         nz = sum_h(nz);
         for (int trial = 0; trial < 64; ++trial) {
+            n_fwd += __popcll(__ballot(active && h == 0));
             const float tau = alpha * lam;
             f4 acc[NZB];
 #pragma unroll
@@ -276,7 +279,12 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
                     d[2 * c] = xb_r - y_r;
                     d[2 * c + 1] = xb_i - y_i;
                     d2 += d[2 * c] * d[2 * c] + d[2 * c + 1] * d[2 * c + 1];
-                    s1 += sqrtf(xb_r * xb_r + xb_i * xb_i);
+                    // |x-bar| - |x^k| without cancellation:
+                    //   (|x-bar|^2 - |x^k|^2) / (|x-bar| + |x^k|)
+                    const float x_r = X[b][2 * c], x_i = X[b][2 * c + 1];
+                    const float den = sqrtf(xb_r * xb_r + xb_i * xb_i) + sqrtf(x_r * x_r + x_i * x_i);
+                    const float num = (xb_r - x_r) * (xb_r + x_r) + (xb_i - x_i) * (xb_i + x_i);
+                    s1 += den > 0.0f ? num * __builtin_amdgcn_rcpf(den) : 0.0f;
                 }
                 const int m0 = m_base + 8 * b + 2 * h;
 #pragma unroll
@@ -334,7 +342,9 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
                     a.status[pix] = st;
                     a.iters[pix] = k - 1;
                     a.kkt32[pix] = bad ? 0.0f : kkt;
-                    if (a.polish && !conv && !bad && !nonfinite) {
+                    // every finite pixel is offered to the FP64 stage, which first checks
+                    // the FP64 KKT residual (the FP32 one carries rounding and drift)
+                    if (a.polish && !bad && !nonfinite) {
                         uint32_t slot = atomicAdd(a.polish_count, 1u);
                         a.polish_list[slot] = (int32_t)pix;
                     }
@@ -362,20 +372,25 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
 
         // ---- monotone acceptance and state rotation (live slots)
         {
-            // residual of x-bar: r(y) + A d, with r(y) = r_k + beta (r_k - r_{k-1})
-            float fb = 0.0f;
+            // residual of x-bar: r(y) + A d, with r(y) = r_k + beta (r_k - r_{k-1}).
+            // Monotone test of Algorithm 1 as the sign of F(x-bar) - F(x^k), formed
+            // from differences so that it is not swamped by the rounding of F:
+            //   ||r-bar||^2 - ||r_k||^2 = <r-bar - r_k, r-bar + r_k>,
+            //   ||x-bar||_1 - ||x^k||_1 = sum (|x-bar| - |x^k|)  (accumulated above).
+            float dfr = 0.0f;
             float Rb[NZB][4];
 #pragma unroll
             for (int ob = 0; ob < NZB; ++ob)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    Rb[ob][r] = R[ob][r] + beta * (R[ob][r] - Rp[ob][r]) + Wt[ob][r];
-                    fb += Rb[ob][r] * Rb[ob][r];
+                    const float dr = beta * (R[ob][r] - Rp[ob][r]) + Wt[ob][r];
+                    Rb[ob][r] = R[ob][r] + dr;
+                    dfr += dr * (Rb[ob][r] + R[ob][r]);
                 }
-            fb = sum_h(fb);
-            const float Fbar = fb + lam * l1;
+            dfr = sum_h(dfr);
+            const float dF = dfr + lam * l1;
             const bool live = active && !retire;
-            const bool accept = live && (!a.monotone || Fbar <= Fk);
+            const bool accept = live && (!a.monotone || dF <= 0.0f);
             const float tau = alpha * lam;
 #pragma unroll
             for (int b = 0; b < KB; ++b)
@@ -403,7 +418,7 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
                     if (live) Rp[ob][r] = R[ob][r];
                     if (accept) R[ob][r] = Rb[ob][r];
                 }
-            if (accept) Fk = Fbar;
+            if (accept) Fk += dF;
             if (live) ++k;
         }
 
@@ -413,6 +428,11 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
         refill(rmask);
         if (__ballot(active) == 0) break;
         adjoint();
+        n_adj += __popcll(__ballot(active && h == 0));
+    }
+    if (tid == 0) {
+        atomicAdd(&a.work[0], n_fwd);
+        atomicAdd(&a.work[1], n_adj);
     }
 }
 
@@ -422,7 +442,7 @@ __global__ void __launch_bounds__(256) fista_kernel(const FistaArgs a)
 // reset the work queue.  One workgroup of 256 threads.
 __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, const float2 *A,
                                                     float2 *Ap, double2 *M, StackConsts *consts,
-                                                    uint32_t *queue)
+                                                    uint32_t *queue, unsigned long long *work)
 {
     __shared__ double red[256];
     __shared__ double2 v[kMaxN];
@@ -430,6 +450,7 @@ __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, con
     __shared__ double ctl[4];
     const int tid = threadIdx.x, bd = blockDim.x;
     if (tid < 4) queue[tid] = 0u;
+    if (tid < 2) work[tid] = 0ull;
     for (int idx = tid; idx < n * l_pad; idx += bd) {
         const int r = idx / l_pad, c = idx % l_pad;
         Ap[idx] = c < l ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
@@ -545,10 +566,11 @@ bool fista_a_fits_lds(int n, int l_pad, int waves, int zb)
 }
 
 hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, double2 *gram,
-                        StackConsts *consts, uint32_t *queue, hipStream_t s)
+                        StackConsts *consts, uint32_t *queue, unsigned long long *work,
+                        hipStream_t s)
 {
     hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, s, n, l, l_pad, A, Ap, gram, consts,
-                       queue);
+                       queue, work);
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct FistaArgs {
     const StackConsts *consts;
     uint32_t *queue;          // [0] next pixel
     uint32_t *polish_count;   // number of pixels appended to polish_list
+    unsigned long long *work; // [0] pixel forward products, [1] pixel adjoint products
     int32_t *polish_list;
     int32_t fista_cap;        // retire unsolved pixels after this many iterations
     float tol, c_alpha;
@@ -67,9 +68,25 @@ struct CertifyArgs {
     int32_t *nnz;
 };
 
+struct PolishArgsDev {
+    int n, l, l_pad;
+    const float2 *A;          // packed n x l_pad
+    const float2 *B;
+    const float *lambda;
+    int64_t lambda_stride;
+    float2 *X;
+    const StackConsts *consts;
+    const uint32_t *count;    // number of listed pixels
+    const int32_t *list;      // pixel indices
+    uint32_t *status;         // workspace status: POLISHED is or-ed in
+    int32_t rounds;
+    int32_t mode;             // 1: refine pixels whose FP64 KKT > tol; 2: refine all
+    float tol;
+};
+
 // Workspace layout for one stack.
 struct StackWorkspace {
-    size_t a_packed, consts, queue, status, iters, kkt32, polish_list, gram, total;
+    size_t a_packed, consts, queue, work, status, iters, kkt32, polish_list, gram, total;
 };
 StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
 
@@ -79,9 +96,11 @@ int lpad_for(int l);           // 8 KB W
 int zblocks_for(int n);
 
 hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, double2 *gram,
-                        StackConsts *consts, uint32_t *queue, hipStream_t s);
+                        StackConsts *consts, uint32_t *queue, unsigned long long *work,
+                        hipStream_t s);
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s);
 hipError_t launch_certify(const CertifyArgs &a, hipStream_t s);
+hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s);
 size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds);
 bool fista_a_fits_lds(int n, int l_pad, int waves, int zb);
 

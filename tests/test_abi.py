@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI (no GPU needed: no call below reaches a launch)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1805_01759_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "l1ls.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(l1ls_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = header_functions()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(_lib.EXPORTS) <= set(names)
+
+
+def test_options_default(L):
+    o = L.l1ls_options_default()
+    assert (o.max_iter, round(o.tol, 8), o.c_alpha, o.precision) == (500, 1e-4, 0.5, 0)
+    assert o.backtracking == 1 and o.monotone == 1 and o.fp64_polish == 1 and o.warm_start == 0
+
+
+def _ws(L, n, l, p, o=None):
+    sz = ctypes.c_size_t(0)
+    st = L.l1ls_workspace_size(n, l, p, ctypes.byref(o) if o else None, ctypes.byref(sz))
+    return st, sz.value
+
+
+def test_workspace_sizes(L):
+    st, a = _ws(L, 25, 256, 1 << 20)
+    assert st == 0 and a > (1 << 20) * 12
+    st, b = _ws(L, 25, 256, 0)
+    assert st == 0 and 0 < b < a
+    assert _ws(L, 0, 10, 1)[0] == -1
+    assert _ws(L, 10, 0, 1)[0] == -1
+    assert _ws(L, 10, 10, -1)[0] == -1
+    assert _ws(L, 65, 100, 1)[0] == -2
+    assert b"supported sizes" in L.l1ls_last_error()
+    assert _ws(L, 10, 513, 1)[0] == -2
+
+
+def _solve(L, n=4, l=8, p=3, o=None, A=16, B=32, lam=64, X=128, ws=256, wsb=1 << 20, stride=0):
+    o = o or L.l1ls_options_default()
+    return L.l1ls_solve(n, l, p, ctypes.c_void_p(A), ctypes.c_void_p(B), ctypes.c_void_p(lam),
+                        stride, ctypes.byref(o), ctypes.c_void_p(X), None, ctypes.c_void_p(ws),
+                        wsb, None)
+
+
+def test_argument_errors_before_any_launch(L):
+    # pointers are fake: every case below must be rejected by validation
+    assert _solve(L, A=0) == -1
+    assert _solve(L, X=0) == -1
+    assert _solve(L, A=12) == -1               # misaligned
+    assert _solve(L, ws=128) == -1             # workspace alignment
+    assert _solve(L, wsb=16) == -3             # workspace too small
+    assert _solve(L, stride=-1) == -1
+    for field, val in [("tol", 0.0), ("tol", float("nan")), ("c_alpha", 1.0), ("c_alpha", 0.0),
+                       ("max_iter", -1), ("precision", 7), ("warm_start", 1), ("fp64_polish", 3)]:
+        o = L.l1ls_options_default()
+        setattr(o, field, val)
+        assert _solve(L, o=o) == -1, field
+    assert _solve(L, n=200) == -2
+    assert L.l1ls_status_string(-3) == b"L1LS_ERR_WORKSPACE"
+
+
+def test_empty_batch_is_a_noop(L):
+    assert _solve(L, p=0, A=0, B=0, lam=0, X=0, ws=0, wsb=0) == 0
