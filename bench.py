@@ -27,12 +27,16 @@ WORKLOADS = {
     "scene": (2, "scene-scale TomoSAR stack: N=25, L=256, P=1048576, baselines U[-300,300] m, "
                  "0/1/2 scatterers (0.3/0.5/0.2), SNR U[0,20] dB, lambda_p = sigma_p sqrt(2 N ln L)"),
     "tiny": (1, "tiny TomoSAR stack: N=15, L=101, P=1024, SNR 10 dB"),
+    "pairs": (4, "close-pair TomoSAR stack: N=50, L=512, P=4194304, 40% two scatterers 0.3-1.0 "
+                 "Rayleigh apart, SNR 10 dB"),
 }
 
 
 def kernel_sha() -> str:
-    src = os.path.join(HERE, "paper_1805_01759_amd", "csrc", "fista.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("fista_impl.h", "fista.hip"):
+        h.update(open(os.path.join(HERE, "paper_1805_01759_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload: str):
@@ -60,17 +64,64 @@ def cpu_baseline(A, B, lam, sample: int, max_iter: int, tol: float):
                       f"tol {tol}, max {max_iter} iterations; {solved} solved in {dt:.1f} s"}
 
 
+def bench_unrolled(args):
+    """Differentiation through K = 200 unrolled fixed-step iterations (N=25, L=256,
+    P=2^18, checkpoints every 20): forward + hand-written adjoint per step."""
+    import torch
+    from paper_1805_01759_amd import synth
+    from paper_1805_01759_amd.unrolled import unrolled
+    p = args.pixels or (1 << 18)
+    spec, geom, B, lam, meta = synth.make_config(5, 0, p, with_meta=True)
+    Xt = synth.xtrue(spec, geom, meta)
+    A = geom.A
+    alpha = 1.0 / (2 * np.linalg.eigvalsh(A @ A.conj().T).max())
+    dev = torch.device("cuda:0")
+    Bd = torch.from_numpy(B.astype(np.complex64)).to(dev)
+    Xtd = torch.from_numpy(Xt.astype(np.complex64)).to(dev)
+    xi = torch.tensor(geom.xi, dtype=torch.float32, device=dev)
+    s = torch.tensor(geom.s, dtype=torch.float32, device=dev)
+    lam_t = torch.tensor(float(lam[0]), dtype=torch.float32, device=dev)
+
+    def step():
+        b = Bd.clone().requires_grad_(True)
+        lt = lam_t.clone().requires_grad_(True)
+        xg = xi.clone().requires_grad_(True)
+        X = unrolled(b, lt, xg, s, alpha, 200, 20)
+        loss = (X - Xtd).abs().pow(2).sum()
+        loss.backward()
+        return xg.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n, l = A.shape
+    flops = 200 * 64.0 * n * l * p  # forward 16NL + recompute 16NL + reverse 32NL per iteration
+    print(json.dumps({"metric": "pixel-gradients/s through 200 unrolled iterations",
+                      "value": p * args.steps / dt, "unit": "pixels/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"unrolled map N={n}, L={l}, P={p}, K=200, ckpt 20",
+                                 "useful_tflops": flops * args.steps / dt / 1e12}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="scene", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="scene", choices=sorted(WORKLOADS) + ["unrolled"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
     ap.add_argument("--max-iter", type=int, default=500)
-    ap.add_argument("--polish-after", type=int, default=200)
+    ap.add_argument("--polish-after", type=int, default=50)
     ap.add_argument("--polish", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (reference for HBM byte counters)")
@@ -91,8 +142,10 @@ def main():
         return
     from paper_1805_01759_amd import api, synth
 
+    if args.workload == "unrolled":
+        return bench_unrolled(args)
     cfg, desc = WORKLOADS[args.workload]
-    spec, geom, B, lam = synth.make_config(cfg)
+    spec, geom, B, lam = synth.make_config(cfg, 0, args.pixels or None)
     A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
     dev = torch.device("cuda:0")
     Ad = torch.from_numpy(A32).to(dev)
@@ -138,7 +191,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "bf16x3",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "l": l, "pixels": p, "max_iter": args.max_iter,
+        "config": {"workload": desc if not args.pixels else desc + f" (first {p} pixels)", "n": n, "l": l, "pixels": p, "max_iter": args.max_iter,
                    "tol": 1e-4, "precision": args.precision, "polish_after": args.polish_after,
                    "solved_fraction": solved / (p * args.steps), "pixels_refined_fp64": npol},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,

@@ -366,28 +366,80 @@ int32_t l1ls_plan_describe(const l1ls_plan *, char *buf, int32_t n)
     if (buf && n > 0) buf[0] = 0;
     return 0;
 }
-l1ls_status l1ls_unrolled_tape_size(int32_t, int32_t, int64_t, int32_t, int32_t, size_t *bytes)
+static l1ls_status check_unrolled(int32_t n, int32_t l, int64_t p, int32_t K, int32_t ckpt)
 {
-    if (bytes) *bytes = 0;
-    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+    if (n < 1 || l < 1 || p < 0) return fail(L1LS_ERR_INVALID_ARG, "need n >= 1, l >= 1, p >= 0");
+    if (K < 1 || ckpt < 1 || K % ckpt != 0)
+        return fail(L1LS_ERR_INVALID_ARG, "need K >= 1, ckpt_every >= 1 dividing K (got %d, %d)", K, ckpt);
+    if (n > 128 || (7 * l + 2 * n) * 8 * 4 > 160 * 1024)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "unrolled map supports n <= 128 and 7 l + 2 n <= 5120");
+    if (p >= ((int64_t)1 << 31)) return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "p must be < 2^31");
+    return L1LS_OK;
 }
-l1ls_status l1ls_unrolled_backward_ws_size(int32_t, int32_t, int64_t, int32_t, int32_t, size_t *bytes)
+
+l1ls_status l1ls_unrolled_tape_size(int32_t n, int32_t l, int64_t p, int32_t K, int32_t ckpt,
+                                    size_t *bytes)
 {
-    if (bytes) *bytes = 0;
-    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+    if (!bytes) return fail(L1LS_ERR_INVALID_ARG, "bytes pointer is NULL");
+    l1ls_status st = check_unrolled(n, l, p, K, ckpt);
+    if (st != L1LS_OK) return st;
+    *bytes = unrolled_tape_bytes(n, l, p, K, ckpt);
+    return L1LS_OK;
 }
-l1ls_status l1ls_unrolled_forward(int32_t, int32_t, int64_t, const float *, const float *,
-                                  const l1ls_c32 *, float, float, int32_t, int32_t, l1ls_c32 *,
-                                  void *, size_t, hipStream_t)
+
+l1ls_status l1ls_unrolled_backward_ws_size(int32_t n, int32_t l, int64_t p, int32_t K, int32_t ckpt,
+                                           size_t *bytes)
 {
-    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+    if (!bytes) return fail(L1LS_ERR_INVALID_ARG, "bytes pointer is NULL");
+    l1ls_status st = check_unrolled(n, l, p, K, ckpt);
+    if (st != L1LS_OK) return st;
+    *bytes = unrolled_bwd_ws_bytes(n, l, p, K, ckpt);
+    return L1LS_OK;
 }
-l1ls_status l1ls_unrolled_backward(int32_t, int32_t, int64_t, const float *, const float *,
-                                   const l1ls_c32 *, float, float, int32_t, int32_t, const void *,
-                                   size_t, const l1ls_c32 *, l1ls_c32 *, float *, float *, void *,
-                                   size_t, hipStream_t)
+
+l1ls_status l1ls_unrolled_forward(int32_t n, int32_t l, int64_t p, const float *xi, const float *s,
+                                  const l1ls_c32 *B, float lambda, float alpha, int32_t K,
+                                  int32_t ckpt, l1ls_c32 *X_K, void *tape, size_t tape_bytes,
+                                  hipStream_t stream)
 {
-    return fail(L1LS_ERR_INTERNAL, "unrolled map is not available in this build");
+    l1ls_status st = check_unrolled(n, l, p, K, ckpt);
+    if (st != L1LS_OK) return st;
+    if (!xi || !s || !tape || (p > 0 && (!B || !X_K)))
+        return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
+    if (!(lambda >= 0.0f) || !isfinite(lambda) || !(alpha > 0.0f) || !isfinite(alpha))
+        return fail(L1LS_ERR_INVALID_ARG, "need finite lambda >= 0 and alpha > 0");
+    if (!aligned(tape, 256)) return fail(L1LS_ERR_INVALID_ARG, "tape must be 256-byte aligned");
+    if (tape_bytes < unrolled_tape_bytes(n, l, p, K, ckpt))
+        return fail(L1LS_ERR_WORKSPACE, "tape too small");
+    hipError_t e = launch_unrolled_forward(n, l, p, xi, s, (const float2 *)B, lambda, alpha, K, ckpt,
+                                           (float2 *)X_K, tape, stream);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "unrolled forward: %s", hipGetErrorString(e));
+    return L1LS_OK;
+}
+
+l1ls_status l1ls_unrolled_backward(int32_t n, int32_t l, int64_t p, const float *xi, const float *s,
+                                   const l1ls_c32 *B, float lambda, float alpha, int32_t K,
+                                   int32_t ckpt, const void *tape, size_t tape_bytes,
+                                   const l1ls_c32 *dX, l1ls_c32 *dB, float *dlambda, float *dxi,
+                                   void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    (void)xi;
+    (void)s;
+    l1ls_status st = check_unrolled(n, l, p, K, ckpt);
+    if (st != L1LS_OK) return st;
+    if (!tape || !dlambda || !dxi || !ws || (p > 0 && (!B || !dX || !dB)))
+        return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
+    if (!(lambda >= 0.0f) || !isfinite(lambda) || !(alpha > 0.0f) || !isfinite(alpha))
+        return fail(L1LS_ERR_INVALID_ARG, "need finite lambda >= 0 and alpha > 0");
+    if (!aligned(ws, 256) || !aligned(tape, 256))
+        return fail(L1LS_ERR_INVALID_ARG, "tape and workspace must be 256-byte aligned");
+    if (tape_bytes < unrolled_tape_bytes(n, l, p, K, ckpt)) return fail(L1LS_ERR_WORKSPACE, "tape too small");
+    if (ws_bytes < unrolled_bwd_ws_bytes(n, l, p, K, ckpt))
+        return fail(L1LS_ERR_WORKSPACE, "workspace too small");
+    hipError_t e = launch_unrolled_backward(n, l, p, (const float2 *)B, lambda, alpha, K, ckpt, tape,
+                                            (const float2 *)dX, (float2 *)dB, dlambda, dxi, ws, stream);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "unrolled backward: %s", hipGetErrorString(e));
+    return L1LS_OK;
 }
 
 }  // extern "C"

@@ -101,6 +101,15 @@ hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, do
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s);
 hipError_t launch_certify(const CertifyArgs &a, hipStream_t s);
 hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s);
+size_t unrolled_tape_bytes(int n, int l, int64_t p, int K, int ckpt);
+size_t unrolled_bwd_ws_bytes(int n, int l, int64_t p, int K, int ckpt);
+hipError_t launch_unrolled_forward(int n, int l, int64_t p, const float *xi, const float *s,
+                                   const float2 *B, float lambda, float alpha, int K, int ckpt,
+                                   float2 *X, void *tape, hipStream_t st);
+hipError_t launch_unrolled_backward(int n, int l, int64_t p, const float2 *B, float lambda,
+                                    float alpha, int K, int ckpt, const void *tape,
+                                    const float2 *dX, float2 *dB, float *dlambda, float *dxi,
+                                    void *ws, hipStream_t st);
 size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds);
 bool fista_a_fits_lds(int n, int l_pad, int waves, int zb);
 

@@ -16,7 +16,7 @@
 
 namespace l1ls {
 
-constexpr int kMaxSupp = 24;          // Newton on at most 24 complex unknowns
+constexpr int kMaxSupp = 16;          // Newton on at most 16 complex unknowns
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
 
 __device__ __forceinline__ double wsum(double v)
@@ -33,8 +33,8 @@ __device__ __forceinline__ double wmax(double v)
 }
 
 struct PolishShared {
-    double2 x[64 * kMaxWavesIter * 2];   // l_pad <= 512
-    double2 best[64 * kMaxWavesIter * 2];
+    double2 *x;       // l_pad entries (dynamic LDS)
+    float2 *best;     // l_pad entries (dynamic LDS): best point, in output precision
     double2 r[kMaxN];
     double2 z[kMaxSupp], zt[kMaxSupp];
     int S[kMaxSupp];
@@ -98,7 +98,13 @@ __device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, const fl
 __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
 {
     __shared__ PolishShared sh;
+    extern __shared__ __align__(16) unsigned char dyn[];
     const int lane = threadIdx.x;
+    if (lane == 0) {
+        sh.x = reinterpret_cast<double2 *>(dyn);
+        sh.best = reinterpret_cast<float2 *>(dyn + (size_t)a.l_pad * sizeof(double2));
+    }
+    __syncthreads();
     const double lf = a.consts->lf;
     const uint32_t count = *a.count;
     for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
@@ -111,7 +117,7 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
         for (int m = lane; m < a.l_pad; m += 64) {
             const float2 v = m < a.l ? xo[m] : make_float2(0.0f, 0.0f);
             sh.x[m] = make_double2(v.x, v.y);
-            sh.best[m] = sh.x[m];
+            sh.best[m] = v;
         }
         __syncthreads();
         // objective and FP64 natural KKT residual of the starting point
@@ -359,7 +365,8 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
             }
             if (F <= fbest) {
                 fbest = F;
-                for (int m = lane; m < a.l_pad; m += 64) sh.best[m] = sh.x[m];
+                for (int m = lane; m < a.l_pad; m += 64)
+                    sh.best[m] = make_float2((float)sh.x[m].x, (float)sh.x[m].y);
             }
             __syncthreads();
             if (kk <= (a.mode == 2 ? 1e-10 : 1e-2 * (double)a.tol)) break;
@@ -383,7 +390,7 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
             if (sh.z[s].x == 0.0 && sh.z[s].y == 0.0) break;
             ++s;
         }
-        for (int m = lane; m < a.l; m += 64) xo[m] = make_float2((float)sh.best[m].x, (float)sh.best[m].y);
+        for (int m = lane; m < a.l; m += 64) xo[m] = sh.best[m];
         if (lane == 0) a.status[p] |= L1LS_PX_POLISHED;
         __syncthreads();
     }
@@ -391,7 +398,15 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
 
 hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s)
 {
-    hipLaunchKernelGGL(polish_kernel, dim3(groups), dim3(64), 0, s, a);
+    const size_t dyn = (size_t)a.l_pad * (sizeof(double2) + sizeof(float2));
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, polish_kernel, 64, dyn);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int g = per_cu > 0 ? per_cu * cus : groups;
+    hipLaunchKernelGGL(polish_kernel, dim3(g), dim3(64), dyn, s, a);
     return hipGetLastError();
 }
 

@@ -202,3 +202,46 @@ def test_scene_scale_sampled(dev, orc):
     assert conv_all.mean() >= 0.9
     conv = conv_all[idx]
     assert (ko[conv] <= 1e-4 * (1 + 1e-5)).all()
+
+
+def test_split_bf16_first_iterations(c1, orc):
+    """Split-BF16 contractions (3 bf16 MFMA passes, FP32 accumulation) track the
+    FP64 iteration to ~2^-16 relative per product."""
+    Ad, Bd, ld = c1["dev"]
+    X, d = api.solve(Ad, Bd, ld, max_iter=5, tol=1e-30, fp64_polish=0, precision="split_bf16")
+    Xg = X.cpu().numpy().astype(np.complex128)
+    Xo, do = orc.rbpg_batch(c1["A64"], c1["B64"], c1["L64"], tol=1e-30, max_iter=5)
+    e = _rel_err(Xg, Xo, c1["A64"], c1["B64"], c1["Lf"])
+    print(f"split-bf16 5 iterations: e p50 {np.median(e):.1e} p99 {np.percentile(e, 99):.1e}")
+    assert np.median(e) < 1e-4
+    assert (e <= 1e-3).mean() >= 0.99
+
+
+def test_split_bf16_exact_mode(c1):
+    """Split-BF16 iteration + FP64 refinement of every pixel: x within 1e-3 of x*."""
+    Ad, Bd, ld = c1["dev"]
+    X, d = api.solve(Ad, Bd, ld, fp64_polish=2, polish_after=100, precision="split_bf16")
+    Xg = X.cpu().numpy().astype(np.complex128)
+    e = _rel_err(Xg, c1["Xe"], c1["A64"], c1["B64"], c1["Lf"])
+    conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
+    assert conv.all()
+    assert (e <= 1e-3).all()
+
+
+def test_close_pairs_sampled(dev, orc):
+    """Close-pair stack (N=50, L=512): FP32 and split-BF16, 128 sampled pixels of
+    the first 8192; per-pixel error against the certified minimiser."""
+    A, B, lam = _case(4, 0, 8192)
+    Ad, Bd, ld = _to_dev(dev, A, B, lam)
+    idx = np.arange(0, 8192, 64)
+    A64 = A.astype(np.complex128)
+    Lf = orc.lipschitz(A64)
+    Xe, de = orc.exact_batch(A64, B[idx].astype(np.complex128), lam[idx].astype(np.float64))
+    for prec, bar in (("fp32", 1e-4), ("split_bf16", 1e-3)):
+        X, d = api.solve(Ad, Bd, ld, fp64_polish=2, polish_after=100, precision=prec)
+        Xg = X.cpu().numpy()[idx].astype(np.complex128)
+        e = _rel_err(Xg, Xe, A64, B[idx].astype(np.complex128), Lf)
+        conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
+        print(f"{prec}: solved {conv.mean():.4f}; e p50 {np.median(e):.1e} p99 {np.percentile(e, 99):.1e} max {e.max():.1e}")
+        assert conv.mean() >= 0.99
+        assert (e <= bar).mean() >= 0.98
