@@ -132,3 +132,69 @@ def timing_read():
     cnt = ctypes.c_int32(0)
     _lib.load().l1ls_timing_read(ctypes.byref(tot), ctypes.byref(cnt))
     return tot.value, cnt.value
+
+
+class Plan:
+    """Batched solve of stacks of uneven shape (each with its own A).
+
+    Built once from the shapes; ``execute`` only enqueues kernels on the
+    stream (no allocation, no synchronisation), so it can be captured into a
+    torch.cuda.CUDAGraph (a HIP graph).
+    """
+
+    def __init__(self, shapes, **opts):
+        L = _lib.load()
+        self.shapes = [(int(n), int(l), int(p)) for n, l, p in shapes]
+        self.opts = options(**opts)
+        arr = (_lib.Stack * max(1, len(self.shapes)))()
+        for i, (n, l, p) in enumerate(self.shapes):
+            arr[i].n, arr[i].l, arr[i].p = n, l, p
+        self._ptr = ctypes.c_void_p()
+        _lib.check(L.l1ls_plan_create(arr, len(self.shapes), ctypes.byref(self.opts),
+                                      ctypes.byref(self._ptr)), "l1ls_plan_create")
+        sz = ctypes.c_size_t(0)
+        _lib.check(L.l1ls_plan_workspace_size(self._ptr, ctypes.byref(sz)), "plan workspace")
+        self.workspace_bytes = sz.value
+
+    def describe(self) -> str:
+        L = _lib.load()
+        need = L.l1ls_plan_describe(self._ptr, None, 0)
+        buf = ctypes.create_string_buffer(max(need, 1))
+        L.l1ls_plan_describe(self._ptr, buf, len(buf))
+        return buf.value.decode()
+
+    def execute(self, stacks, workspace: torch.Tensor, stream=None):
+        """stacks: list of dicts with A, B, lam (tensor), X and diag tensors."""
+        L = _lib.load()
+        arr = (_lib.Stack * max(1, len(stacks)))()
+        keep = []
+        for i, st in enumerate(stacks):
+            n, l, p = self.shapes[i]
+            A, B, lam_t, stride = _check_inputs(st["A"], st["B"], st["lam"])
+            keep += [A, B, lam_t]
+            d = st["diag"]
+            arr[i].n, arr[i].l, arr[i].p = n, l, p
+            arr[i].A, arr[i].B, arr[i].lambda_ = A.data_ptr(), B.data_ptr(), lam_t.data_ptr()
+            arr[i].lambda_stride = stride
+            arr[i].X = st["X"].data_ptr()
+            arr[i].diag = _lib.Diag(d["iters"].data_ptr(), d["kkt"].data_ptr(),
+                                    d["objective"].data_ptr(), d["status"].data_ptr(),
+                                    d["nnz"].data_ptr())
+        self._keep = keep
+        _lib.check(L.l1ls_plan_execute(self._ptr, arr, _ptr(workspace), workspace.numel(),
+                                       _stream(stream)), "l1ls_plan_execute")
+
+    def __del__(self):
+        try:
+            if getattr(self, "_ptr", None) and self._ptr.value:
+                _lib.load().l1ls_plan_destroy(self._ptr)
+        except Exception:
+            pass
+
+
+def new_diag(p: int, device):
+    return {"iters": torch.empty(p, dtype=torch.int32, device=device),
+            "kkt": torch.empty(p, dtype=torch.float32, device=device),
+            "objective": torch.empty(p, dtype=torch.float32, device=device),
+            "status": torch.empty(p, dtype=torch.int32, device=device),
+            "nnz": torch.empty(p, dtype=torch.int32, device=device)}

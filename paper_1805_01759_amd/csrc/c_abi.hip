@@ -62,9 +62,21 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     return w;
 }
 
-// Largest supported shapes of the persistent kernel.
-constexpr int kMaxNSolve = 64;    // 2N <= 8 MFMA row blocks
-constexpr int kMaxLSolve = 512;   // 8 waves of 64 unknowns
+// Largest supported shapes: the register-resident MFMA kernel takes N <= 64,
+// L <= 512; the wave-per-pixel kernel takes the rest up to N = 128, L = 1024.
+constexpr int kMaxNSolve = 128;
+constexpr int kMaxLSolve = 1024;
+
+bool mfma_supports(int n, int l) { return n <= 64 && l <= 512; }
+
+l1ls_status set_error(l1ls_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
 
 static l1ls_status check_options(const l1ls_options *o)
 {
@@ -119,10 +131,10 @@ struct TimedLaunch {
     }
 };
 
-static l1ls_status solve_impl(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
-                              const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
-                              l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
-                              hipStream_t s)
+l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                        const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                        l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
+                        hipStream_t s, int choice)
 {
     l1ls_status st = check_shape(n, l, p);
     if (st != L1LS_OK) return st;
@@ -180,9 +192,12 @@ static l1ls_status solve_impl(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A
     fa.backtracking = opt->backtracking ? 1 : 0;
     fa.monotone = opt->monotone ? 1 : 0;
     fa.polish = opt->fp64_polish;
+    if (choice == kAuto) choice = mfma_supports(n, l) ? kMfma : kWave;
+    if (choice == kMfma && !mfma_supports(n, l))
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
     {
         TimedLaunch t(s);
-        e = launch_fista(fa, opt->precision, 0, s);
+        e = choice == kMfma ? launch_fista(fa, opt->precision, 0, s) : launch_fista_wave(fa, s);
     }
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
 
@@ -275,8 +290,8 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
                        l1ls_c32 *X, const l1ls_diag *diag, void *workspace, size_t ws_bytes,
                        hipStream_t stream)
 {
-    return solve_impl(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, workspace, ws_bytes,
-                      stream);
+    return solve_stack(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, workspace, ws_bytes,
+                       stream, kAuto);
 }
 
 const char *l1ls_status_string(l1ls_status s)
@@ -344,28 +359,6 @@ int32_t l1ls_timing_read(double *total_ms, int32_t *launches)
     return cnt;
 }
 
-// ---- entry points still to be provided by later kernels
-struct l1ls_plan { int dummy; };
-l1ls_status l1ls_plan_create(const l1ls_stack *, int32_t, const l1ls_options *, l1ls_plan **out)
-{
-    if (out) *out = nullptr;
-    return fail(L1LS_ERR_INTERNAL, "batched plans are not available in this build");
-}
-l1ls_status l1ls_plan_workspace_size(const l1ls_plan *, size_t *bytes)
-{
-    if (bytes) *bytes = 0;
-    return fail(L1LS_ERR_INTERNAL, "batched plans are not available in this build");
-}
-l1ls_status l1ls_plan_execute(l1ls_plan *, const l1ls_stack *, void *, size_t, hipStream_t)
-{
-    return fail(L1LS_ERR_INTERNAL, "batched plans are not available in this build");
-}
-void l1ls_plan_destroy(l1ls_plan *) {}
-int32_t l1ls_plan_describe(const l1ls_plan *, char *buf, int32_t n)
-{
-    if (buf && n > 0) buf[0] = 0;
-    return 0;
-}
 static l1ls_status check_unrolled(int32_t n, int32_t l, int64_t p, int32_t K, int32_t ckpt)
 {
     if (n < 1 || l < 1 || p < 0) return fail(L1LS_ERR_INVALID_ARG, "need n >= 1, l >= 1, p >= 0");

@@ -1,0 +1,240 @@
+// Wave-per-pixel form of the accelerated proximal-gradient iteration (complex
+// L1LS of arXiv 1805.01759, Algorithm 1 with one block), for shapes outside
+// the register-resident MFMA kernel (N up to 128, L up to 1024).  It follows
+// the same reading of the algorithm as that kernel:
+//   beta_k = max(0, (k-2)/(k+1));  y = x^k + beta (x^k - x^{k-1});
+//   grad f(y) = G_k + beta (G_k - G_{k-1})       (grad f is affine)
+//   x-bar = S_{alpha lambda}(y - alpha grad f(y));  d = x-bar - y;  w = A d
+//   Eq. (15) for quadratic f:  ||A d||^2 <= ||d||^2 / (2 alpha), else alpha *= C_alpha
+//   accept iff F(x-bar) - F(x^k) <= 0, formed from differences
+//   r_{k+1} = r(y) + w,  G_{k+1} = 2 A^H r_{k+1}
+// The pixel's state lives in LDS (one wave per workgroup); A is read from the
+// packed workspace copy (L2-resident: it is shared by every pixel).
+#include "l1ls_internal.h"
+
+namespace l1ls {
+
+__device__ __forceinline__ float wsumf(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wmaxf(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ void cprox_w(float vr, float vi, float tau, float &o_r, float &o_i)
+{
+    const float m = sqrtf(vr * vr + vi * vi);
+    const float sc = m > tau ? 1.0f - tau / m : 0.0f;
+    o_r = vr * sc;
+    o_i = vi * sc;
+}
+
+#define WAVE_SYNC()                          \
+    do {                                     \
+        __builtin_amdgcn_wave_barrier();     \
+        __builtin_amdgcn_s_waitcnt(0);       \
+        __builtin_amdgcn_wave_barrier();     \
+    } while (0)
+
+__global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int n = a.n, l = a.l, ld = a.l_pad;
+    float2 *X = reinterpret_cast<float2 *>(smem);
+    float2 *Xp = X + l;
+    float2 *G = Xp + l;
+    float2 *Gp = G + l;
+    float2 *D = Gp + l;       // d = x-bar - y of the current trial
+    float2 *R = D + l;        // r_k (n)
+    float2 *Rp = R + n;       // r_{k-1}
+    float2 *W = Rp + n;       // A d
+    const float lf = (float)a.consts->lf;
+    const float inv_lf = (float)(1.0 / a.consts->lf);
+    const float alpha0 = (float)a.consts->alpha0;
+    const float afloor = inv_lf;
+    unsigned long long n_fwd = 0, n_adj = 0;
+
+    for (;;) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.queue, 1u);
+        base = __shfl(base, 0, 64);
+        if ((int64_t)base >= a.p) break;
+        const int64_t pix = base;
+        float lam = a.lambda[pix * a.lambda_stride];
+        const bool bad = !(lam > 0.0f) || !isfinite(lam);
+        if (bad) lam = 1.0f;
+        const float2 *b = a.B + (size_t)pix * n;
+        for (int j = lane; j < l; j += 64) X[j] = Xp[j] = Gp[j] = make_float2(0.0f, 0.0f);
+        float bb = 0.0f;
+        for (int i = lane; i < n; i += 64) {
+            const float2 v = b[i];
+            R[i] = Rp[i] = make_float2(-v.x, -v.y);
+            bb += v.x * v.x + v.y * v.y;
+        }
+        float Fk = wsumf(bb);
+        WAVE_SYNC();
+        // G = 2 A^H r
+        for (int j = lane; j < l; j += 64) {
+            float gr = 0.0f, gi = 0.0f;
+            for (int i = 0; i < n; ++i) {
+                const float2 av = a.A[(size_t)i * ld + j], rv = R[i];
+                gr = fmaf(av.x, rv.x, fmaf(av.y, rv.y, gr));
+                gi = fmaf(av.x, rv.y, fmaf(-av.y, rv.x, gi));
+            }
+            G[j] = make_float2(2.0f * gr, 2.0f * gi);
+        }
+        ++n_adj;
+        WAVE_SYNC();
+        float alpha = alpha0;
+        int k = 1;
+        float kkt = 0.0f;
+        bool conv = false, nonfinite = false;
+        for (;;) {
+            // natural KKT residual at x^k with G_k
+            float kmax = 0.0f;
+            for (int j = lane; j < l; j += 64) {
+                const float2 x = X[j], g = G[j];
+                float p_r, p_i;
+                cprox_w(x.x - g.x * inv_lf, x.y - g.y * inv_lf, lam * inv_lf, p_r, p_i);
+                const float e_r = x.x - p_r, e_i = x.y - p_i;
+                kmax = fmaxf(kmax, e_r * e_r + e_i * e_i);
+            }
+            kkt = lf * sqrtf(wmaxf(kmax)) / lam;
+            nonfinite = !isfinite(kkt) || !isfinite(Fk);
+            conv = kkt <= a.tol;
+            if (bad || nonfinite || conv || (k - 1) >= a.fista_cap) break;
+            const float beta = fmaxf(0.0f, (float)(k - 2) / (float)(k + 1));
+            float d2 = 0.0f, dl1 = 0.0f;
+            for (int trial = 0; trial < 64; ++trial) {
+                const float tau = alpha * lam;
+                d2 = 0.0f;
+                dl1 = 0.0f;
+                for (int j = lane; j < l; j += 64) {
+                    const float2 x = X[j], xp = Xp[j], g = G[j], gp = Gp[j];
+                    const float y_r = x.x + beta * (x.x - xp.x), y_i = x.y + beta * (x.y - xp.y);
+                    const float gy_r = g.x + beta * (g.x - gp.x), gy_i = g.y + beta * (g.y - gp.y);
+                    float xb_r, xb_i;
+                    cprox_w(y_r - alpha * gy_r, y_i - alpha * gy_i, tau, xb_r, xb_i);
+                    const float d_r = xb_r - y_r, d_i = xb_i - y_i;
+                    D[j] = make_float2(d_r, d_i);
+                    d2 += d_r * d_r + d_i * d_i;
+                    const float den = sqrtf(xb_r * xb_r + xb_i * xb_i) + sqrtf(x.x * x.x + x.y * x.y);
+                    const float num = (xb_r - x.x) * (xb_r + x.x) + (xb_i - x.y) * (xb_i + x.y);
+                    dl1 += den > 0.0f ? num / den : 0.0f;
+                }
+                d2 = wsumf(d2);
+                dl1 = wsumf(dl1);
+                WAVE_SYNC();
+                // w = A d (lanes over n)
+                float w2 = 0.0f;
+                for (int i = lane; i < n; i += 64) {
+                    float wr = 0.0f, wi = 0.0f;
+                    const float2 *row = a.A + (size_t)i * ld;
+                    for (int j = 0; j < l; ++j) {
+                        const float2 av = row[j], dv = D[j];
+                        wr = fmaf(av.x, dv.x, fmaf(-av.y, dv.y, wr));
+                        wi = fmaf(av.x, dv.y, fmaf(av.y, dv.x, wi));
+                    }
+                    W[i] = make_float2(wr, wi);
+                    w2 += wr * wr + wi * wi;
+                }
+                w2 = wsumf(w2);
+                ++n_fwd;
+                WAVE_SYNC();
+                if (!(a.backtracking && w2 > d2 / (2.0f * alpha) && alpha > afloor)) break;
+                alpha = fmaxf(a.c_alpha * alpha, afloor);
+            }
+            // monotone acceptance from differences
+            float dfr = 0.0f;
+            for (int i = lane; i < n; i += 64) {
+                const float2 r = R[i], rp = Rp[i], w = W[i];
+                const float dr_r = beta * (r.x - rp.x) + w.x, dr_i = beta * (r.y - rp.y) + w.y;
+                dfr += dr_r * (2.0f * r.x + dr_r) + dr_i * (2.0f * r.y + dr_i);
+            }
+            const float dF = wsumf(dfr) + lam * dl1;
+            const bool accept = !a.monotone || dF <= 0.0f;
+            for (int i = lane; i < n; i += 64) {
+                const float2 r = R[i], rp = Rp[i], w = W[i];
+                Rp[i] = r;
+                if (accept)
+                    R[i] = make_float2(r.x + beta * (r.x - rp.x) + w.x, r.y + beta * (r.y - rp.y) + w.y);
+            }
+            for (int j = lane; j < l; j += 64) {
+                const float2 x = X[j], xp = Xp[j], d = D[j];
+                Xp[j] = x;
+                Gp[j] = G[j];
+                if (accept)
+                    X[j] = make_float2(x.x + beta * (x.x - xp.x) + d.x, x.y + beta * (x.y - xp.y) + d.y);
+            }
+            if (accept) Fk += dF;
+            ++k;
+            WAVE_SYNC();
+            for (int j = lane; j < l; j += 64) {
+                float gr = 0.0f, gi = 0.0f;
+                for (int i = 0; i < n; ++i) {
+                    const float2 av = a.A[(size_t)i * ld + j], rv = R[i];
+                    gr = fmaf(av.x, rv.x, fmaf(av.y, rv.y, gr));
+                    gi = fmaf(av.x, rv.y, fmaf(-av.y, rv.x, gi));
+                }
+                G[j] = make_float2(2.0f * gr, 2.0f * gi);
+            }
+            ++n_adj;
+            WAVE_SYNC();
+        }
+        // retire
+        float2 *xo = a.X + (size_t)pix * l;
+        for (int j = lane; j < l; j += 64) xo[j] = X[j];
+        if (lane == 0) {
+            uint32_t st = 0;
+            if (bad) st |= L1LS_PX_BAD_LAMBDA;
+            else if (nonfinite) st |= L1LS_PX_NONFINITE;
+            else if (!conv) st |= L1LS_PX_MAX_ITER;
+            a.status[pix] = st;
+            a.iters[pix] = k - 1;
+            a.kkt32[pix] = bad ? 0.0f : kkt;
+            if (a.polish && !bad && !nonfinite) {
+                const uint32_t slot = atomicAdd(a.polish_count, 1u);
+                a.polish_list[slot] = (int32_t)pix;
+            }
+        }
+        WAVE_SYNC();
+    }
+    if (lane == 0) {
+        atomicAdd(&a.work[0], n_fwd);
+        atomicAdd(&a.work[1], n_adj);
+    }
+}
+
+size_t fista_wave_lds(int n, int l) { return (size_t)(5 * l + 3 * n) * sizeof(float2); }
+
+hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s)
+{
+    const size_t lds = fista_wave_lds(a.n, a.l);
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipFuncSetAttribute((const void *)fista_wave_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_done = true;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fista_wave_kernel, 64, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t groups = (int64_t)per_cu * cus;
+    if (groups > a.p) groups = a.p;
+    if (groups < 1) groups = 1;
+    hipLaunchKernelGGL(fista_wave_kernel, dim3((unsigned)groups), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace l1ls

@@ -99,6 +99,17 @@ hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, do
                         StackConsts *consts, uint32_t *queue, unsigned long long *work,
                         hipStream_t s);
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s);
+hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s);
+size_t fista_wave_lds(int n, int l);
+
+// Which iteration kernel runs a stack.
+enum KernelChoice { kAuto = 0, kMfma = 1, kWave = 2 };
+bool mfma_supports(int n, int l);
+l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                        const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                        l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
+                        hipStream_t s, int choice);
+l1ls_status set_error(l1ls_status st, const char *fmt, ...);
 hipError_t launch_certify(const CertifyArgs &a, hipStream_t s);
 hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s);
 size_t unrolled_tape_bytes(int n, int l, int64_t p, int K, int ckpt);
