@@ -1,6 +1,9 @@
 """Build libl1ls.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1805_01759_amd.build   (or build() from Python)
+Usage: python -m paper_1805_01759_amd.build [--incremental]   (or build() from Python)
+
+--incremental recompiles only sources whose object is older than the source
+or than any header under csrc/ or include/.
 """
 from __future__ import annotations
 
@@ -39,11 +42,32 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    inc = os.path.join(ROOT, "include")
+    hs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _stale(src: str, hdr: float) -> bool:
+    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(src) or t < hdr
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sources()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    todo = srcs
+    if incremental:
+        hdr = _headers_mtime()
+        todo = [s for s in srcs if _stale(s, hdr)]
+    if todo:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
+            list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD_DIR, os.path.basename(s) + ".o") for s in srcs]
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,5 +80,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

@@ -9,19 +9,26 @@
 //       2 [[Re G, -Im G], [Im G, Re G]] + lambda blkdiag((I - u u^T)/|z_s|),
 //     G = A_S^H A_S, u = (Re z_s, Im z_s)/|z_s|; the coordinate whose Newton step
 //     turns it round most leaves the working set; Armijo backtracking on phi;
+//     Newton stops once the working-set gradient is below the target or the
+//     predicted decrease is below FP64 rounding of phi (then the full step is
+//     taken: a line search there only measures rounding noise);
 //   * full FP64 gradient: natural KKT residual, and the worst off-set
 //     violator of |g_l| <= lambda enters at its exact coordinate minimiser,
 // until the KKT residual is at the target or no violator is left.  The point
 // with the least objective is kept and written back (complex64).
 //
-// The working set's columns A_S are staged in LDS, so phi, its gradient and the
-// Hessian read LDS only; the full-gradient pass reads A coalesced.
+// LDS holds the best point (complex64), the working set's columns A_S, the
+// residual and a packed lower-triangular Hessian; the dense iterate is never
+// materialised (a per-bin index into the working set stands in for it), which
+// keeps the footprint near 12 KB at N=25, L=256 so that many pixels are in
+// flight per CU.
 #include "l1ls_internal.h"
 
 namespace l1ls {
 
 constexpr int kMaxSupp = 16;          // Newton on at most 16 complex unknowns
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
+constexpr int kTri = kMaxM * (kMaxM + 1) / 2;
 
 __device__ __forceinline__ double wsum(double v)
 {
@@ -35,16 +42,25 @@ __device__ __forceinline__ double wmax(double v)
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
+// value of v held by lane i (i uniform across the wave)
+__device__ __forceinline__ double lane_value(double v, int i)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }  // k <= i
 
 struct PolishShared {
-    double2 *x;       // l_pad entries (dynamic LDS): dense iterate
-    float2 *best;     // l_pad entries (dynamic LDS): best point, in output precision
-    float2 *AS;       // n x kMaxSupp (dynamic LDS): columns of the working set
-    double2 r[kMaxN];
+    double2 *r;         // n: residual A x - b (dynamic LDS)
+    float2 *best;       // l_pad: best point so far / starting point (dynamic LDS)
+    float2 *AS;         // n x kMaxSupp: columns of the working set (dynamic LDS)
+    int16_t *nzl;       // l_pad: nonzero bins of the starting point (dynamic LDS)
+    int8_t *sidx;       // l_pad: slot of bin m in the working set, or -1 (dynamic LDS)
+    double H[kTri];     // packed lower triangle of the real Hessian / its Cholesky factor
     double2 z[kMaxSupp], zt[kMaxSupp];
+    double grd[kMaxM], dir[kMaxM];
     int S[kMaxSupp];
-    double H[kMaxM * kMaxM];
-    double rhs[kMaxM], grd[kMaxM], hdiag[kMaxM];
     int cnt;
 };
 
@@ -66,21 +82,37 @@ __device__ void stage_col(const PolishArgsDev &a, PolishShared &sh, int t, int m
     for (int nn = threadIdx.x; nn < a.n; nn += 64) sh.AS[nn * kMaxSupp + t] = a.A[(size_t)nn * a.l_pad + m];
 }
 
-// r = A x - b over the dense x in LDS (zero entries skipped, uniform branch)
-__device__ void residual_dense(const PolishArgsDev &a, PolishShared &sh, const float2 *b)
+// r = A x0 - b for the starting point (its nonzero bins listed first)
+__device__ void residual_start(const PolishArgsDev &a, PolishShared &sh, const float2 *b)
 {
     const int lane = threadIdx.x;
-    for (int nn = lane; nn < a.n; nn += 64) {
-        double rr = 0.0, ri = 0.0;
-        for (int m = 0; m < a.l; ++m) {
-            const double2 xv = sh.x[m];
-            if (xv.x != 0.0 || xv.y != 0.0) {
-                const double2 av = Aat(a, nn, m);
-                rr += av.x * xv.x - av.y * xv.y;
-                ri += av.x * xv.y + av.y * xv.x;
-            }
+    if (lane == 0) sh.cnt = 0;
+    __syncthreads();
+    for (int m0 = 0; m0 < a.l; m0 += 64) {
+        const int m = m0 + lane;
+        bool nz = false;
+        if (m < a.l) {
+            const float2 v = sh.best[m];
+            nz = v.x != 0.0f || v.y != 0.0f;
         }
-        sh.r[nn] = make_double2(rr - b[nn].x, ri - b[nn].y);
+        const uint64_t bal = __ballot(nz);
+        const int base = sh.cnt;
+        if (nz) sh.nzl[base + __popcll(bal & ((1ull << lane) - 1ull))] = (int16_t)m;
+        __syncthreads();
+        if (lane == 0) sh.cnt = base + __popcll(bal);
+        __syncthreads();
+    }
+    const int cnt = sh.cnt;
+    for (int nn = lane; nn < a.n; nn += 64) {
+        double rr = -(double)b[nn].x, ri = -(double)b[nn].y;
+        for (int q = 0; q < cnt; ++q) {
+            const int m = sh.nzl[q];
+            const float2 xf = sh.best[m];
+            const double2 av = Aat(a, nn, m);
+            rr += av.x * xf.x - av.y * xf.y;
+            ri += av.x * xf.y + av.y * xf.x;
+        }
+        sh.r[nn] = make_double2(rr, ri);
     }
     __syncthreads();
 }
@@ -109,8 +141,11 @@ __device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, const fl
     return out;
 }
 
-// Full FP64 pass at the dense x (with sh.r its residual): natural KKT residual,
-// objective, and the worst off-support violator of |g| <= lambda.
+// Full FP64 pass at the current point (sh.r its residual): natural KKT
+// residual, objective, and the worst off-support violator of |g| <= lambda.
+// START: the point is the starting iterate in sh.best; else it is z on the
+// working set (sh.sidx).
+template <bool START>
 __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, double lam, double lf,
                           double &F, double &kk, int &vidx)
 {
@@ -119,7 +154,17 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, double lam, 
     vidx = -1;
     for (int nn = lane; nn < a.n; nn += 64) acc += sh.r[nn].x * sh.r[nn].x + sh.r[nn].y * sh.r[nn].y;
     for (int m = lane; m < a.l; m += 64) {
-        const double xr = sh.x[m].x, xi = sh.x[m].y;
+        double xr, xi;
+        if (START) {
+            const float2 v = sh.best[m];
+            xr = v.x;
+            xi = v.y;
+        } else {
+            const int t = sh.sidx[m];
+            const double2 v = t >= 0 ? sh.z[t] : make_double2(0.0, 0.0);
+            xr = v.x;
+            xi = v.y;
+        }
         l1 += sqrt(xr * xr + xi * xi);
         double gr = 0.0, gi = 0.0;
         for (int nn = 0; nn < a.n; ++nn) {
@@ -152,18 +197,119 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, double lam, 
     }
 }
 
+// Packed lower triangle of 2 realify(A_S^H A_S) + lambda blkdiag((I - u u^T)/|z|) + mu I.
+// Lanes are split into 64/E groups over the rows of A_S when the s x s entries
+// fit E = 16 lanes; the group partial sums are combined with shuffles.
+__device__ void build_hessian(const PolishArgsDev &a, PolishShared &sh, int s, double lam, double mu)
+{
+    const int lane = threadIdx.x;
+    const int ne = s * s;
+    const bool grouped = ne <= 16;
+    const int E = grouped ? 16 : 64, G = grouped ? 4 : 1;
+    const int q = lane / E;
+    for (int e0 = 0; e0 < ne; e0 += E) {
+        const int e = e0 + lane % E;
+        const bool act = e < ne;
+        const int t = act ? e / s : 0, u = act ? e % s : 0;
+        double gr = 0.0, gi = 0.0;
+        if (act) {
+            for (int nn = q; nn < a.n; nn += G) {
+                const double2 p1 = ASat(sh, nn, t), p2 = ASat(sh, nn, u);
+                gr += p1.x * p2.x + p1.y * p2.y;  // conj(p1) p2
+                gi += p1.x * p2.y - p1.y * p2.x;
+            }
+        }
+        if (grouped) {
+            gr += __shfl_xor(gr, 16, 64);
+            gi += __shfl_xor(gi, 16, 64);
+            gr += __shfl_xor(gr, 32, 64);
+            gi += __shfl_xor(gi, 32, 64);
+        }
+        if (act && q == 0) {
+            double h00 = 2.0 * gr, h11 = 2.0 * gr, h10 = 2.0 * gi;
+            if (t == u) {
+                const double2 zv = sh.z[t];
+                const double az = sqrt(zv.x * zv.x + zv.y * zv.y);
+                const double ur = zv.x / az, ui = zv.y / az;
+                h00 += lam * (1.0 - ur * ur) / az + mu;
+                h11 += lam * (1.0 - ui * ui) / az + mu;
+                h10 -= lam * ur * ui / az;
+            }
+            if (t >= u) {
+                sh.H[tri(t, u)] = h00;
+                sh.H[tri(t + s, u + s)] = h11;
+            }
+            sh.H[tri(t + s, u)] = h10;
+        }
+    }
+    __syncthreads();
+}
+
+// In-place Cholesky of the packed matrix of order m2; false if not positive definite.
+__device__ bool cholesky(PolishShared &sh, int m2)
+{
+    const int lane = threadIdx.x;
+    bool good = true;
+    for (int jj = 0; jj < m2; ++jj) {
+        double djj = sh.H[tri(jj, jj)];
+        for (int k = 0; k < jj; ++k) djj -= sh.H[tri(jj, k)] * sh.H[tri(jj, k)];
+        if (!(djj > 0.0)) {
+            good = false;
+            break;
+        }
+        djj = sqrt(djj);
+        for (int i = jj + 1 + lane; i < m2; i += 64) {
+            double t = sh.H[tri(i, jj)];
+            for (int k = 0; k < jj; ++k) t -= sh.H[tri(i, k)] * sh.H[tri(jj, k)];
+            sh.H[tri(i, jj)] = t / djj;
+        }
+        __syncthreads();
+        if (lane == 0) sh.H[tri(jj, jj)] = djj;
+    }
+    __syncthreads();
+    return good;
+}
+
+// Solve L L^T d = -grd with the factor in sh.H; lane k ends holding d_k
+// (column-oriented substitutions, one broadcast per column).
+__device__ double newton_dir(const PolishShared &sh, int m2)
+{
+    const int lane = threadIdx.x;
+    double v = lane < m2 ? -sh.grd[lane] : 0.0;
+    for (int i = 0; i < m2; ++i) {
+        const double yi = lane_value(v, i) / sh.H[tri(i, i)];
+        if (lane == i) v = yi;
+        else if (lane > i && lane < m2) v -= sh.H[tri(lane, i)] * yi;
+    }
+    for (int i = m2 - 1; i >= 0; --i) {
+        const double di = lane_value(v, i) / sh.H[tri(i, i)];
+        if (lane == i) v = di;
+        else if (lane < i) v -= sh.H[tri(i, lane)] * di;
+    }
+    return v;
+}
+
 __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
 {
     __shared__ PolishShared sh;
     extern __shared__ __align__(16) unsigned char dyn[];
     const int lane = threadIdx.x;
     if (lane == 0) {
-        sh.x = reinterpret_cast<double2 *>(dyn);
-        sh.best = reinterpret_cast<float2 *>(dyn + (size_t)a.l_pad * sizeof(double2));
-        sh.AS = reinterpret_cast<float2 *>(dyn + (size_t)a.l_pad * (sizeof(double2) + sizeof(float2)));
+        unsigned char *p = dyn;
+        sh.r = reinterpret_cast<double2 *>(p);
+        p += (size_t)a.n * sizeof(double2);
+        sh.best = reinterpret_cast<float2 *>(p);
+        p += (size_t)a.l_pad * sizeof(float2);
+        sh.AS = reinterpret_cast<float2 *>(p);
+        p += (size_t)a.n * kMaxSupp * sizeof(float2);
+        sh.nzl = reinterpret_cast<int16_t *>(p);
+        p += (size_t)a.l_pad * sizeof(int16_t);
+        sh.sidx = reinterpret_cast<int8_t *>(p);
     }
     __syncthreads();
     const double lf = a.consts->lf;
+    const double gstop = a.mode == 2 ? 1e-13 : 1e-3 * (double)a.tol;
+    const double kstop = a.mode == 2 ? 1e-10 : 1e-2 * (double)a.tol;
     const uint32_t count = *a.count;
     for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
         const int64_t p = a.list[item];
@@ -173,16 +319,15 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
         const float2 *b = a.B + (size_t)p * a.n;
         float2 *xo = a.X + (size_t)p * a.l;
         for (int m = lane; m < a.l_pad; m += 64) {
-            const float2 v = m < a.l ? xo[m] : make_float2(0.0f, 0.0f);
-            sh.x[m] = make_double2(v.x, v.y);
-            sh.best[m] = v;
+            sh.best[m] = m < a.l ? xo[m] : make_float2(0.0f, 0.0f);
+            sh.sidx[m] = -1;
         }
         __syncthreads();
         // objective and FP64 natural KKT residual of the starting point
-        residual_dense(a, sh, b);
+        residual_start(a, sh, b);
         double fbest, kk0;
         int vdummy;
-        full_pass(a, sh, lam, lf, fbest, kk0, vdummy);
+        full_pass<true>(a, sh, lam, lf, fbest, kk0, vdummy);
         __syncthreads();
         if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
         // -- working set: the local maxima of |x| (FISTA spreads one scatterer
@@ -193,10 +338,12 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
             const int m = m0 + lane;
             bool pk = false;
             if (m < a.l) {
-                const double2 xv = sh.x[m];
-                const double mag = xv.x * xv.x + xv.y * xv.y;
-                const double ml = m > 0 ? sh.x[m - 1].x * sh.x[m - 1].x + sh.x[m - 1].y * sh.x[m - 1].y : 0.0;
-                const double mr = m + 1 < a.l ? sh.x[m + 1].x * sh.x[m + 1].x + sh.x[m + 1].y * sh.x[m + 1].y : 0.0;
+                const float2 xv = sh.best[m];
+                const float2 xl = m > 0 ? sh.best[m - 1] : make_float2(0.0f, 0.0f);
+                const float2 xr = m + 1 < a.l ? sh.best[m + 1] : make_float2(0.0f, 0.0f);
+                const double mag = (double)xv.x * xv.x + (double)xv.y * xv.y;
+                const double ml = (double)xl.x * xl.x + (double)xl.y * xl.y;
+                const double mr = (double)xr.x * xr.x + (double)xr.y * xr.y;
                 pk = mag > 0.0 && mag >= ml && mag >= mr;
             }
             const uint64_t bal = __ballot(pk);
@@ -207,7 +354,8 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
                     const int q = __ffsll((unsigned long long)bits) - 1;
                     bits &= bits - 1;
                     const int mm = m0 + q;
-                    const double2 xv = sh.x[mm];
+                    const float2 xf = sh.best[mm];
+                    const double2 xv = make_double2(xf.x, xf.y);
                     const double mag = xv.x * xv.x + xv.y * xv.y;
                     const int s = sh.cnt;
                     if (s < kMaxSupp) {
@@ -237,103 +385,57 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
             for (int it = 0; it < 50 && s > 0; ++it) {
                 const int m2 = 2 * s;
                 const double ph = phi_support(a, sh, b, sh.z, s, lam);
-                // gradient of phi on the working set (real pairs)
+                // gradient of phi on the working set (real pairs); 4 lane groups
+                // over the rows of A_S
                 double gmax = 0.0;
-                for (int t = lane; t < s; t += 64) {
+                {
+                    const int t = lane & 15, q = lane >> 4;
                     double gr = 0.0, gi = 0.0;
-                    for (int nn = 0; nn < a.n; ++nn) {
-                        const double2 av = ASat(sh, nn, t), rv = sh.r[nn];
-                        gr += av.x * rv.x + av.y * rv.y;
-                        gi += av.x * rv.y - av.y * rv.x;
+                    if (t < s) {
+                        for (int nn = q; nn < a.n; nn += 4) {
+                            const double2 av = ASat(sh, nn, t), rv = sh.r[nn];
+                            gr += av.x * rv.x + av.y * rv.y;
+                            gi += av.x * rv.y - av.y * rv.x;
+                        }
                     }
-                    const double2 zv = sh.z[t];
-                    const double az = sqrt(zv.x * zv.x + zv.y * zv.y);
-                    gr = 2.0 * gr + lam * zv.x / az;
-                    gi = 2.0 * gi + lam * zv.y / az;
-                    sh.grd[t] = gr;
-                    sh.grd[t + s] = gi;
-                    gmax = fmax(gmax, sqrt(gr * gr + gi * gi));
+                    gr += __shfl_xor(gr, 16, 64);
+                    gi += __shfl_xor(gi, 16, 64);
+                    gr += __shfl_xor(gr, 32, 64);
+                    gi += __shfl_xor(gi, 32, 64);
+                    if (t < s) {
+                        const double2 zv = sh.z[t];
+                        const double az = sqrt(zv.x * zv.x + zv.y * zv.y);
+                        gr = 2.0 * gr + lam * zv.x / az;
+                        gi = 2.0 * gi + lam * zv.y / az;
+                        if (q == 0) {
+                            sh.grd[t] = gr;
+                            sh.grd[t + s] = gi;
+                        }
+                        gmax = sqrt(gr * gr + gi * gi);
+                    }
                 }
                 gmax = wmax(gmax);
                 __syncthreads();
-                if (gmax <= 1e-13 * lam) break;
-                // Hessian: 2 realify(A_S^H A_S) + lambda (I - u u^T)/|z|
-                for (int e = lane; e < s * s; e += 64) {
-                    const int t = e / s, u = e % s;
-                    double gr = 0.0, gi = 0.0;
-                    for (int nn = 0; nn < a.n; ++nn) {
-                        const double2 p1 = ASat(sh, nn, t), p2 = ASat(sh, nn, u);
-                        gr += p1.x * p2.x + p1.y * p2.y;  // conj(p1) p2
-                        gi += p1.x * p2.y - p1.y * p2.x;
-                    }
-                    sh.H[t * m2 + u] = 2.0 * gr;
-                    sh.H[(t + s) * m2 + (u + s)] = 2.0 * gr;
-                    sh.H[t * m2 + (u + s)] = -2.0 * gi;
-                    sh.H[(t + s) * m2 + u] = 2.0 * gi;
-                }
-                __syncthreads();
-                for (int t = lane; t < s; t += 64) {
-                    const double2 zv = sh.z[t];
-                    const double az = sqrt(zv.x * zv.x + zv.y * zv.y);
-                    const double ur = zv.x / az, ui = zv.y / az;
-                    sh.H[t * m2 + t] += lam * (1.0 - ur * ur) / az;
-                    sh.H[(t + s) * m2 + (t + s)] += lam * (1.0 - ui * ui) / az;
-                    sh.H[t * m2 + (t + s)] -= lam * ur * ui / az;
-                    sh.H[(t + s) * m2 + t] -= lam * ur * ui / az;
-                }
-                __syncthreads();
-                for (int i = lane; i < m2; i += 64) sh.hdiag[i] = sh.H[i * m2 + i];
-                __syncthreads();
-                // Cholesky (lower, in place, upper triangle kept); shifted retry if not PD
+                if (gmax <= gstop * lam) break;
+                // Newton direction; shifted retries while the Hessian is not PD
                 double mu = 0.0;
                 bool ok = false;
                 for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
-                    if (attempt > 0) {
-                        for (int e = lane; e < m2 * m2; e += 64) {
-                            const int i = e / m2, k = e % m2;
-                            if (k < i) sh.H[i * m2 + k] = sh.H[k * m2 + i];
-                            if (k == i) sh.H[i * m2 + i] = sh.hdiag[i] + mu;
-                        }
-                        __syncthreads();
-                    }
-                    bool good = true;
-                    for (int jj = 0; jj < m2; ++jj) {
-                        double djj = sh.H[jj * m2 + jj];
-                        for (int k = 0; k < jj; ++k) djj -= sh.H[jj * m2 + k] * sh.H[jj * m2 + k];
-                        if (!(djj > 0.0)) { good = false; break; }
-                        djj = sqrt(djj);
-                        for (int i = jj + 1 + lane; i < m2; i += 64) {
-                            double t = sh.H[i * m2 + jj];
-                            for (int k = 0; k < jj; ++k) t -= sh.H[i * m2 + k] * sh.H[jj * m2 + k];
-                            sh.H[i * m2 + jj] = t / djj;
-                        }
-                        __syncthreads();
-                        if (lane == 0) sh.H[jj * m2 + jj] = djj;
-                        __syncthreads();
-                    }
-                    ok = good;
+                    build_hessian(a, sh, s, lam, mu);
+                    ok = cholesky(sh, m2);
                     mu = mu == 0.0 ? 1e-14 * lf : mu * 100.0;
-                    __syncthreads();
                 }
                 if (!ok) break;
-                // solve L L^T d = -g (lane 0, order <= 32); find the coordinate the
-                // step turns round most
+                const double dv = newton_dir(sh, m2);
+                if (lane < m2) sh.dir[lane] = dv;
+                __syncthreads();
+                // the coordinate the step turns round most leaves the working set
                 if (lane == 0) {
-                    for (int i = 0; i < m2; ++i) {
-                        double t = -sh.grd[i];
-                        for (int k = 0; k < i; ++k) t -= sh.H[i * m2 + k] * sh.rhs[k];
-                        sh.rhs[i] = t / sh.H[i * m2 + i];
-                    }
-                    for (int i = m2 - 1; i >= 0; --i) {
-                        double t = sh.rhs[i];
-                        for (int k = i + 1; k < m2; ++k) t -= sh.H[k * m2 + i] * sh.rhs[k];
-                        sh.rhs[i] = t / sh.H[i * m2 + i];
-                    }
                     int drop = -1;
                     double worst = 0.0;
                     for (int t = 0; t < s; ++t) {
                         const double2 zv = sh.z[t];
-                        const double nr = zv.x + sh.rhs[t], ni = zv.y + sh.rhs[t + s];
+                        const double nr = zv.x + sh.dir[t], ni = zv.y + sh.dir[t + s];
                         const double c = (zv.x * nr + zv.y * ni) / (zv.x * zv.x + zv.y * zv.y);
                         if (c <= 0.0 && (drop < 0 || c < worst)) { drop = t; worst = c; }
                     }
@@ -355,15 +457,20 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
                     --s;
                     continue;
                 }
+                const double slope = wsum(lane < m2 ? sh.grd[lane] * dv : 0.0);
+                if (-slope <= 1e-14 * ph) {
+                    // predicted decrease below the rounding of phi: take the step, stop
+                    for (int t = lane; t < s; t += 64)
+                        sh.z[t] = make_double2(sh.z[t].x + sh.dir[t], sh.z[t].y + sh.dir[t + s]);
+                    __syncthreads();
+                    break;
+                }
                 // Armijo backtracking on phi
-                double slope = 0.0;
-                for (int t = lane; t < m2; t += 64) slope += sh.grd[t] * sh.rhs[t];
-                slope = wsum(slope);
                 double step = 1.0;
                 bool acc = false;
                 for (int ls = 0; ls < 40; ++ls) {
                     for (int t = lane; t < s; t += 64)
-                        sh.zt[t] = make_double2(sh.z[t].x + step * sh.rhs[t], sh.z[t].y + step * sh.rhs[t + s]);
+                        sh.zt[t] = make_double2(sh.z[t].x + step * sh.dir[t], sh.z[t].y + step * sh.dir[t + s]);
                     __syncthreads();
                     const double pn = phi_support(a, sh, b, sh.zt, s, lam);
                     if (pn <= ph + 1e-4 * step * slope) { acc = true; break; }
@@ -373,22 +480,24 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
                 for (int t = lane; t < s; t += 64) sh.z[t] = sh.zt[t];
                 __syncthreads();
             }
-            // scatter the working set into the dense x; residual from the working set
-            for (int m = lane; m < a.l_pad; m += 64) sh.x[m] = make_double2(0.0, 0.0);
-            __syncthreads();
-            for (int t = lane; t < s; t += 64) sh.x[sh.S[t]] = sh.z[t];
+            // the working set as the current point; its residual
+            for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = (int8_t)t;
             __syncthreads();
             phi_support(a, sh, b, sh.z, s, lam);
             double F, kk;
             int vidx;
-            full_pass(a, sh, lam, lf, F, kk, vidx);
+            full_pass<false>(a, sh, lam, lf, F, kk, vidx);
             if (F <= fbest) {
                 fbest = F;
-                for (int m = lane; m < a.l_pad; m += 64)
-                    sh.best[m] = make_float2((float)sh.x[m].x, (float)sh.x[m].y);
+                for (int m = lane; m < a.l_pad; m += 64) {
+                    const int t = sh.sidx[m];
+                    sh.best[m] = t >= 0 ? make_float2((float)sh.z[t].x, (float)sh.z[t].y) : make_float2(0.0f, 0.0f);
+                }
             }
             __syncthreads();
-            if (kk <= (a.mode == 2 ? 1e-10 : 1e-2 * (double)a.tol)) break;
+            for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = -1;
+            __syncthreads();
+            if (kk <= kstop) break;
             if (vidx < 0 || s >= kMaxSupp) break;
             // the worst violator enters at its exact coordinate minimiser
             stage_col(a, sh, s, vidx);
@@ -416,10 +525,15 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
     }
 }
 
+size_t polish_lds_bytes(int n, int l_pad)
+{
+    return (size_t)n * sizeof(double2) + (size_t)l_pad * (sizeof(float2) + sizeof(int16_t) + sizeof(int8_t)) +
+           (size_t)n * kMaxSupp * sizeof(float2);
+}
+
 hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s)
 {
-    const size_t dyn = (size_t)a.l_pad * (sizeof(double2) + sizeof(float2)) +
-                       (size_t)a.n * kMaxSupp * sizeof(float2);
+    const size_t dyn = polish_lds_bytes(a.n, a.l_pad);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, polish_kernel, 64, dyn);
     if (e != hipSuccess) return e;
