@@ -34,7 +34,7 @@ WORKLOADS = {
 
 def kernel_sha() -> str:
     h = hashlib.sha256()
-    for f in ("fista_impl.h", "fista.hip"):
+    for f in ("fista_mfma.h", "fista_impl.h", "fista.hip"):
         h.update(open(os.path.join(HERE, "paper_1805_01759_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -252,7 +252,8 @@ def main():
                    "solved_fraction": solved / (p * args.steps), "pixels_refined_fp64": npol},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
-                     "traffic": traffic, "kernel": "fista_kernel",
+                     "traffic": traffic,
+                     "kernel": "fista_mfma_kernel" if args.precision == "fp32" else "fista_kernel",
                      "kernel_ms": k_avg_s * 1e3,
                      "flops_per_launch": flops},
     }

@@ -34,6 +34,7 @@ int waves_for(int l)
 }
 int lpad_for(int l) { return waves_for(l) * 8 * slice_blocks_for(l); }
 int zblocks_for(int n) { return (2 * n + 15) / 16; }
+int rows_pad_for(int n) { return 16 * ((n + 15) / 16); }
 
 StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
 {
@@ -41,7 +42,7 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     const int l_pad = lpad_for(l);
     size_t off = 0;
     w.a_packed = off;
-    off = align_up(off + (size_t)n * l_pad * sizeof(float2), 256);
+    off = align_up(off + (size_t)rows_pad_for(n) * l_pad * sizeof(float2), 256);
     w.gram = off;
     off = align_up(off + (size_t)n * n * sizeof(double2), 256);
     w.consts = off;

@@ -6,9 +6,13 @@ namespace l1ls {
 
 template <int NZB, int KB, bool ALDS, int PREC>
 hipError_t launch_one(const FistaArgs &a, int max_groups, hipStream_t s);
+template <int T, int KB, bool ALDS>
+hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s);
+
+__device__ __forceinline__ int rows_pad_for_dev(int n) { return 16 * ((n + 15) / 16); }
 
 // ---------------------------------------------------------------------------
-// Setup: pack A (zero-padded columns), alpha0 = 1/(2 max_l ||a_l||^2),
+// Setup: pack A (zero-padded rows to a multiple of 16, zero-padded columns), alpha0 = 1/(2 max_l ||a_l||^2),
 // L_f = 2 lambda_max(A A^H) by FP64 power iteration on the Gram matrix, and
 // reset the work queue.  One workgroup of 256 threads.
 __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, const float2 *A,
@@ -22,9 +26,10 @@ __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, con
     const int tid = threadIdx.x, bd = blockDim.x;
     if (tid < 4) queue[tid] = 0u;
     if (tid < 2) work[tid] = 0ull;
-    for (int idx = tid; idx < n * l_pad; idx += bd) {
+    const int rows = rows_pad_for_dev(n);
+    for (int idx = tid; idx < rows * l_pad; idx += bd) {
         const int r = idx / l_pad, c = idx % l_pad;
-        Ap[idx] = c < l ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
+        Ap[idx] = (r < n && c < l) ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
     }
     double cm = 0.0;
     for (int c = tid; c < l; c += bd) {
@@ -172,10 +177,39 @@ static hipError_t launch_prec(const FistaArgs &a, int max_groups, hipStream_t s)
     }
 }
 
+// FP32 contractions: the kernel with split real/imaginary accumulators
+size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds)
+{
+    const int rows = rows_pad_for(n), T = rows / 16;
+    size_t off = a_lds ? (((size_t)rows * (l_pad + 2) * sizeof(float2) + 15) & ~(size_t)15) : 0;
+    off += (size_t)waves * 2 * T * 64 * 16;
+    off += (size_t)waves * 16 * 16;
+    off += 16;
+    return off;
+}
+
+template <int T>
+static hipError_t launch_mfma_t(const FistaArgs &a, int max_groups, hipStream_t s)
+{
+    // one wave per SIMD: a workgroup of W waves may use W/4 of the CU's 160 KB
+    const bool lds = fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, true) <= (size_t)160 * 1024 * a.waves / 4;
+    if (slice_blocks_for(a.l) == 8)
+        return lds ? launch_mfma_one<T, 4, true>(a, max_groups, s)
+                   : launch_mfma_one<T, 4, false>(a, max_groups, s);
+    return lds ? launch_mfma_one<T, 8, true>(a, max_groups, s)
+               : launch_mfma_one<T, 8, false>(a, max_groups, s);
+}
+
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s)
 {
     if (precision == L1LS_SPLIT_BF16) return launch_prec<L1LS_SPLIT_BF16>(a, max_groups, s);
-    return launch_prec<L1LS_FP32>(a, max_groups, s);
+    switch (rows_pad_for(a.n) / 16) {
+    case 1: return launch_mfma_t<1>(a, max_groups, s);
+    case 2: return launch_mfma_t<2>(a, max_groups, s);
+    case 3: return launch_mfma_t<3>(a, max_groups, s);
+    case 4: return launch_mfma_t<4>(a, max_groups, s);
+    default: return launch_prec<L1LS_FP32>(a, max_groups, s);
+    }
 }
 
 }  // namespace l1ls

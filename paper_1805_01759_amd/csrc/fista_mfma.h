@@ -1,0 +1,500 @@
+// Persistent accelerated proximal-gradient kernel (FP32 contractions) for the
+// complex L1LS problem of Shi, Zhu, Yin, Bamler (arXiv 1805.01759), gfx950.
+//
+// One workgroup owns a tile of 16 pixel slots and W <= 4 waves (one per SIMD);
+// wave w owns the complex unknowns [16 KB w, 16 KB (w + 1)) of every slot.  Per
+// slot it runs Algorithm 1 with one block (J = 1):
+//   y      = x^k + beta_k (x^k - x^{k-1}),  beta_k = max(0, (k-2)/(k+1))   Eqs. (11)-(12)
+//   x-bar  = S_{alpha lambda}(y - alpha grad f(y))                          Eqs. (10), (12)
+//   shrink alpha by C_alpha until Eq. (15) holds                            Eq. (15)
+//   accept x-bar only if F(x-bar) <= F(x^k)                                  Algorithm 1
+// with f(x) = ||Ax - b||^2, grad f = 2 A^H (A x - b).
+//
+// Register layout (the output layout of v_mfma_f32_16x16x4f32: lane l holds
+// rows 4 (l/16) + q, q = 0..3, of column l%16).  Lane (j = lane%16, h = lane/16):
+//   unknowns  block b, q:  m = 16 KB w + 16 b + 4 h + q of pixel slot j,
+//             real and imaginary parts in separate vectors (X_re[b][q], X_im[b][q]);
+//   residual  block t, q:  n = 16 t + 4 h + q of pixel slot j (R_re[t][q], R_im[t][q]).
+// Both contractions take A directly as the MFMA A operand (a plain load, no
+// per-element selects or masks: A is zero padded to 16 T rows), and the complex
+// arithmetic is spread over separate real and imaginary accumulators:
+//   forward  W = A d:     W_re += A_re d_re + A_im (-d_im),  W_im += A_im d_re + A_re d_im
+//            (A operand: row n = 16 t + j, k-slot h <-> m = 16 b + 4 h + q; the k-slots
+//            are exactly the unknowns the lane holds, so d feeds the B operand as is)
+//   adjoint  G = 2 A^H r: G_re += A_re (2 r_re) + A_im (2 r_im),
+//                         G_im += A_re (2 r_im) + A_im (-2 r_re)
+//            (A operand: row m = 16 b + j, k-slot h <-> n = 16 t + 4 h + q)
+// so each wave issues 16 T KB MFMAs per product and almost no VALU for operands.
+//
+// grad f is affine in x, so grad f(y) = G_k + beta (G_k - G_{k-1}) needs no
+// product; one adjoint per accepted step gives G_{k+1} and with it the exact
+// KKT residual of x^{k+1}.  For quadratic f the condition of Eq. (15) at
+// (y, x-bar) is identical to ||A d||^2 <= ||d||^2 / (2 alpha) (the linear terms
+// cancel), which is evaluated from the forward product of d.  The monotone
+// test is the sign of F(x-bar) - F(x^k) formed from differences:
+//   ||r-bar||^2 - ||r_k||^2 = <r-bar - r_k, r-bar + r_k>,
+//   ||x-bar||_1 - ||x^k||_1 = sum_m (|x-bar_m| - |x^k_m|)   (|x^k_m| kept per unknown).
+//
+// Pixels retire when the FP32 KKT residual passes tol, or after fista_cap
+// iterations; a retired slot is refilled at once from a global atomic queue.
+#pragma once
+#include "l1ls_internal.h"
+
+namespace l1ls {
+
+namespace fm {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Sum / max over the four lanes (h = 0..3) that hold one pixel slot.
+__device__ __forceinline__ float sum_h(float v)
+{
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+__device__ __forceinline__ float max_h(float v)
+{
+    v = fmaxf(v, __shfl_xor(v, 16, 64));
+    v = fmaxf(v, __shfl_xor(v, 32, 64));
+    return v;
+}
+
+// One complex unknown of the trial: extrapolate, gradient step, prox
+// S_tau(v) = v max(0, 1 - tau/|v|).  Returns x-bar and |x-bar|; shared by the
+// trial and the acceptance so that both produce bit-identical values.
+__device__ __forceinline__ void trial_one(float x_r, float x_i, float xp_r, float xp_i, float g_r,
+                                          float g_i, float gp_r, float gp_i, float beta,
+                                          float alpha, float tau, float &y_r, float &y_i,
+                                          float &xb_r, float &xb_i, float &axb)
+{
+    y_r = fmaf(beta, x_r - xp_r, x_r);
+    y_i = fmaf(beta, x_i - xp_i, x_i);
+    const float gy_r = fmaf(beta, g_r - gp_r, g_r);
+    const float gy_i = fmaf(beta, g_i - gp_i, g_i);
+    const float v_r = fmaf(-alpha, gy_r, y_r);
+    const float v_i = fmaf(-alpha, gy_i, y_i);
+    const float m2 = fmaf(v_r, v_r, v_i * v_i);
+    const float rs = __builtin_amdgcn_rsqf(m2);
+    const bool keep = m2 > tau * tau;          // |v| > tau; 0/0 of the rsq is discarded
+    const float sc = keep ? fmaf(-tau, rs, 1.0f) : 0.0f;
+    xb_r = v_r * sc;
+    xb_i = v_i * sc;
+    axb = keep ? fmaf(m2, rs, -tau) : 0.0f;    // |v| - tau
+}
+
+// A as the MFMA A operand: LDS copy (row stride ld) or the packed global copy.
+struct AView {
+    const float2 *p;
+    int ld;
+    __device__ __forceinline__ f4 load4(int row, int m) const
+    {
+        return *reinterpret_cast<const f4 *>(p + row * ld + m);
+    }
+    __device__ __forceinline__ float2 load2(int row, int m) const { return p[row * ld + m]; }
+};
+
+}  // namespace fm
+
+// LDS row stride of the staged A (float2 units): l_pad + 2 spreads the rows of
+// one load over distinct banks.
+__host__ __device__ inline int fm_lds_ld(int l_pad) { return l_pad + 2; }
+
+template <int T, int KB, bool ALDS>
+__global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
+{
+    using fm::f4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int W = a.waves;
+    const int j = lane & 15;
+    const int h = lane >> 4;
+    const int n = a.n;
+    const int l = a.l;
+    const int rows = 16 * T;
+
+    size_t off = 0;
+    float2 *sA = reinterpret_cast<float2 *>(smem);
+    if (ALDS) off = ((size_t)rows * fm_lds_ld(a.l_pad) * sizeof(float2) + 15) & ~(size_t)15;
+    f4 *sPW = reinterpret_cast<f4 *>(smem + off);   // [W][2T][64] forward partials
+    off += (size_t)W * 2 * T * 64 * sizeof(f4);
+    f4 *sPS = reinterpret_cast<f4 *>(smem + off);   // [W][16] per-slot partial scalars
+    off += (size_t)W * 16 * sizeof(f4);
+    uint32_t *sQ = reinterpret_cast<uint32_t *>(smem + off);
+
+    fm::AView Av;
+    if (ALDS) {
+        const int ld = fm_lds_ld(a.l_pad), half = a.l_pad / 2;
+        for (int idx = tid; idx < rows * half; idx += blockDim.x) {
+            const int row = idx / half, c2 = idx % half;
+            *reinterpret_cast<f4 *>(sA + (size_t)row * ld + 2 * c2) =
+                *reinterpret_cast<const f4 *>(a.A + (size_t)row * a.l_pad + 2 * c2);
+        }
+        Av.p = sA;
+        Av.ld = ld;
+    } else {
+        Av.p = a.A;
+        Av.ld = a.l_pad;
+    }
+
+    const double lf_d = a.consts->lf;
+    const float lf = (float)lf_d;
+    const float inv_lf = (float)(1.0 / lf_d);
+    const float alpha0 = (float)a.consts->alpha0;
+    const float afloor = inv_lf;
+    const int m_base = w * 16 * KB;
+
+    float Xr[KB][4], Xi[KB][4], Xpr[KB][4], Xpi[KB][4];
+    float Gr[KB][4], Gi[KB][4], Gpr[KB][4], Gpi[KB][4];
+    float AX[KB][4];                                   // |x^k_m|
+    float Rr[T][4], Ri[T][4], Rpr[T][4], Rpi[T][4];    // residual A x - b of x^k, x^{k-1}
+#pragma unroll
+    for (int b = 0; b < KB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            Xr[b][q] = Xi[b][q] = Xpr[b][q] = Xpi[b][q] = Gr[b][q] = Gi[b][q] = Gpr[b][q] =
+                Gpi[b][q] = AX[b][q] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Rr[t][q] = Ri[t][q] = Rpr[t][q] = Rpi[t][q] = 0.0f;
+
+    int64_t pix = -1;
+    int k = 1;
+    float alpha = alpha0, lam = 1.0f, Fk = 0.0f;
+    bool active = false, bad = false, qdone = false;
+
+    // ---- refill the slots in `mask` from the global queue (workgroup-uniform)
+    auto refill = [&](uint32_t mask) {
+        if (mask == 0) return;
+        if (qdone) {
+            if ((mask >> j) & 1u) { active = false; pix = -1; }
+            return;
+        }
+        const uint32_t nfree = __popc(mask);
+        __syncthreads();
+        if (tid == 0) sQ[0] = atomicAdd(a.queue, nfree);
+        __syncthreads();
+        const uint64_t base = sQ[0];
+        if (base + nfree >= (uint64_t)a.p) qdone = true;
+        if ((mask >> j) & 1u) {
+            const uint64_t np = base + (uint64_t)__popc(mask & ((1u << j) - 1u));
+            if (np < (uint64_t)a.p) {
+                pix = (int64_t)np;
+                active = true;
+                k = 1;
+                alpha = alpha0;
+                lam = a.lambda[pix * a.lambda_stride];
+                bad = !(lam > 0.0f) || !isfinite(lam);
+                if (bad) lam = 1.0f;
+#pragma unroll
+                for (int b = 0; b < KB; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        Xr[b][q] = Xi[b][q] = Xpr[b][q] = Xpi[b][q] = Gr[b][q] = Gi[b][q] =
+                            Gpr[b][q] = Gpi[b][q] = AX[b][q] = 0.0f;
+                float bb = 0.0f;
+                const float2 *Bp = a.B + (size_t)pix * n;
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int nn = 16 * t + 4 * h + q;
+                        const float2 v = nn < n ? Bp[nn] : make_float2(0.0f, 0.0f);
+                        Rr[t][q] = Rpr[t][q] = -v.x;
+                        Ri[t][q] = Rpi[t][q] = -v.y;
+                        bb = fmaf(v.x, v.x, fmaf(v.y, v.y, bb));
+                    }
+                Fk = fm::sum_h(bb);
+            } else {
+                active = false;
+                pix = -1;
+            }
+        }
+    };
+
+    // ---- G = 2 A^H r for the wave's unknowns (all slots)
+    auto adjoint = [&]() {
+        float r2r[T][4], r2i[T][4], nr2r[T][4];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                r2r[t][q] = 2.0f * Rr[t][q];
+                r2i[t][q] = 2.0f * Ri[t][q];
+                nr2r[t][q] = -2.0f * Rr[t][q];
+            }
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+            f4 gr = f4{0.0f, 0.0f, 0.0f, 0.0f}, gi = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            const int m = m_base + 16 * b + j;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float2 av = Av.load2(16 * t + 4 * h + q, m);
+                    gr = fm::mfma(av.x, r2r[t][q], gr);
+                    gr = fm::mfma(av.y, r2i[t][q], gr);
+                    gi = fm::mfma(av.x, r2i[t][q], gi);
+                    gi = fm::mfma(av.y, nr2r[t][q], gi);
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Gr[b][q] = gr[q];
+                Gi[b][q] = gi[q];
+            }
+        }
+    };
+
+    unsigned long long n_fwd = 0, n_adj = 0;  // pixel products (thread 0 counts)
+    refill(0xFFFFu);
+    if (__ballot(active) == 0) return;
+    adjoint();
+    n_adj += __popcll(__ballot(active && h == 0));
+
+    for (;;) {
+        const float beta = fmaxf(0.0f, (float)(k - 2) / (float)(k + 1));
+        bool first = true, retire = false, conv = false, nonfinite = false;
+        float kkt = 0.0f, l1 = 0.0f;
+        f4 Wr[T], Wi[T];
+        // natural KKT residual of x^k with its exact gradient G_k
+        float kmax = 0.0f;
+        {
+            const float tk = lam * inv_lf;
+#pragma unroll
+            for (int b = 0; b < KB; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float x_r = Xr[b][q], x_i = Xi[b][q];
+                    const float v_r = fmaf(-inv_lf, Gr[b][q], x_r);
+                    const float v_i = fmaf(-inv_lf, Gi[b][q], x_i);
+                    const float m2 = fmaf(v_r, v_r, v_i * v_i);
+                    const float sc = m2 > tk * tk ? fmaf(-tk, __builtin_amdgcn_rsqf(m2), 1.0f) : 0.0f;
+                    const float e_r = fmaf(-v_r, sc, x_r), e_i = fmaf(-v_i, sc, x_i);
+                    kmax = fmaxf(kmax, fmaf(e_r, e_r, e_i * e_i));
+                }
+            kmax = fm::max_h(kmax);
+        }
+        for (int trial = 0; trial < 64; ++trial) {
+            n_fwd += __popcll(__ballot(active && h == 0));
+            const float tau = alpha * lam;
+#pragma unroll
+            for (int t = 0; t < T; ++t) Wr[t] = Wi[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            float d2 = 0.0f, s1 = 0.0f;
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                float dr[4], di[4], ndi[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float y_r, y_i, xb_r, xb_i, axb;
+                    fm::trial_one(Xr[b][q], Xi[b][q], Xpr[b][q], Xpi[b][q], Gr[b][q], Gi[b][q],
+                                  Gpr[b][q], Gpi[b][q], beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
+                    dr[q] = xb_r - y_r;
+                    di[q] = xb_i - y_i;
+                    ndi[q] = -di[q];
+                    d2 = fmaf(dr[q], dr[q], fmaf(di[q], di[q], d2));
+                    s1 += axb - AX[b][q];
+                }
+                const int m0 = m_base + 16 * b + 4 * h;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const f4 a01 = Av.load4(16 * t + j, m0);      // (re, im) of m0, m0 + 1
+                    const f4 a23 = Av.load4(16 * t + j, m0 + 2);  // (re, im) of m0 + 2, m0 + 3
+                    Wr[t] = fm::mfma(a01[0], dr[0], Wr[t]);
+                    Wr[t] = fm::mfma(a01[1], ndi[0], Wr[t]);
+                    Wi[t] = fm::mfma(a01[1], dr[0], Wi[t]);
+                    Wi[t] = fm::mfma(a01[0], di[0], Wi[t]);
+                    Wr[t] = fm::mfma(a01[2], dr[1], Wr[t]);
+                    Wr[t] = fm::mfma(a01[3], ndi[1], Wr[t]);
+                    Wi[t] = fm::mfma(a01[3], dr[1], Wi[t]);
+                    Wi[t] = fm::mfma(a01[2], di[1], Wi[t]);
+                    Wr[t] = fm::mfma(a23[0], dr[2], Wr[t]);
+                    Wr[t] = fm::mfma(a23[1], ndi[2], Wr[t]);
+                    Wi[t] = fm::mfma(a23[1], dr[2], Wi[t]);
+                    Wi[t] = fm::mfma(a23[0], di[2], Wi[t]);
+                    Wr[t] = fm::mfma(a23[2], dr[3], Wr[t]);
+                    Wr[t] = fm::mfma(a23[3], ndi[3], Wr[t]);
+                    Wi[t] = fm::mfma(a23[3], dr[3], Wi[t]);
+                    Wi[t] = fm::mfma(a23[2], di[3], Wi[t]);
+                }
+            }
+            // cross-wave reduction of the forward partial products and scalars
+            d2 = fm::sum_h(d2);
+            s1 = fm::sum_h(s1);
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                sPW[((size_t)w * 2 * T + 2 * t) * 64 + lane] = Wr[t];
+                sPW[((size_t)w * 2 * T + 2 * t + 1) * 64 + lane] = Wi[t];
+            }
+            if (h == 0) sPS[w * 16 + j] = f4{d2, s1, kmax, 0.0f};
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < T; ++t) Wr[t] = Wi[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            f4 S = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int ww = 0; ww < W; ++ww) {
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    Wr[t] += sPW[((size_t)ww * 2 * T + 2 * t) * 64 + lane];
+                    Wi[t] += sPW[((size_t)ww * 2 * T + 2 * t + 1) * 64 + lane];
+                }
+                const f4 ps = sPS[ww * 16 + j];
+                S[0] += ps[0];
+                S[1] += ps[1];
+                S[2] = fmaxf(S[2], ps[2]);
+            }
+            __syncthreads();
+            float w2 = 0.0f;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w2 = fmaf(Wr[t][q], Wr[t][q], fmaf(Wi[t][q], Wi[t][q], w2));
+            w2 = fm::sum_h(w2);
+            if (first) {
+                kkt = lf * sqrtf(S[2]) / lam;
+                nonfinite = !isfinite(kkt) || !isfinite(Fk);
+                conv = kkt <= a.tol;
+                const bool capped = (k - 1) >= a.fista_cap;
+                retire = active && (bad || nonfinite || conv || capped);
+                if (retire && w == 0 && h == 0) {
+                    uint32_t st = 0;
+                    if (bad) st |= L1LS_PX_BAD_LAMBDA;
+                    else if (nonfinite) st |= L1LS_PX_NONFINITE;
+                    else if (!conv) st |= L1LS_PX_MAX_ITER;
+                    a.status[pix] = st;
+                    a.iters[pix] = k - 1;
+                    a.kkt32[pix] = bad ? 0.0f : kkt;
+                    // every finite pixel is offered to the FP64 stage, which first checks
+                    // the FP64 KKT residual (the FP32 one carries rounding and drift)
+                    if (a.polish && !bad && !nonfinite) {
+                        const uint32_t slot = atomicAdd(a.polish_count, 1u);
+                        a.polish_list[slot] = (int32_t)pix;
+                    }
+                }
+                first = false;
+            }
+            l1 = S[1];
+            const bool fail = active && !retire && a.backtracking && (w2 > S[0] / (2.0f * alpha)) &&
+                              alpha > afloor;
+            if (__ballot(fail) == 0) break;
+            if (fail) alpha = fmaxf(a.c_alpha * alpha, afloor);
+        }
+
+        // ---- retire: write x^k of the wave's unknowns
+        if (retire) {
+            float2 *Xo = a.X + (size_t)pix * l;
+#pragma unroll
+            for (int b = 0; b < KB; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = m_base + 16 * b + 4 * h + q;
+                    if (m < l) Xo[m] = make_float2(Xr[b][q], Xi[b][q]);
+                }
+        }
+
+        // ---- monotone acceptance and state rotation (live slots)
+        {
+            // residual of x-bar: r(y) + A d, with r(y) = r_k + beta (r_k - r_{k-1})
+            float dfr = 0.0f;
+            float Rbr[T][4], Rbi[T][4];
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float dr_r = fmaf(beta, Rr[t][q] - Rpr[t][q], Wr[t][q]);
+                    const float dr_i = fmaf(beta, Ri[t][q] - Rpi[t][q], Wi[t][q]);
+                    Rbr[t][q] = Rr[t][q] + dr_r;
+                    Rbi[t][q] = Ri[t][q] + dr_i;
+                    dfr = fmaf(dr_r, Rbr[t][q] + Rr[t][q], fmaf(dr_i, Rbi[t][q] + Ri[t][q], dfr));
+                }
+            dfr = fm::sum_h(dfr);
+            const float dF = fmaf(lam, l1, dfr);
+            const bool live = active && !retire;
+            const bool accept = live && (!a.monotone || dF <= 0.0f);
+            const float tau = alpha * lam;
+#pragma unroll
+            for (int b = 0; b < KB; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float y_r, y_i, xb_r, xb_i, axb;
+                    fm::trial_one(Xr[b][q], Xi[b][q], Xpr[b][q], Xpi[b][q], Gr[b][q], Gi[b][q],
+                                  Gpr[b][q], Gpi[b][q], beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
+                    if (live) {
+                        Xpr[b][q] = Xr[b][q];
+                        Xpi[b][q] = Xi[b][q];
+                        Gpr[b][q] = Gr[b][q];
+                        Gpi[b][q] = Gi[b][q];
+                    }
+                    if (accept) {
+                        Xr[b][q] = xb_r;
+                        Xi[b][q] = xb_i;
+                        AX[b][q] = axb;
+                    }
+                }
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (live) {
+                        Rpr[t][q] = Rr[t][q];
+                        Rpi[t][q] = Ri[t][q];
+                    }
+                    if (accept) {
+                        Rr[t][q] = Rbr[t][q];
+                        Ri[t][q] = Rbi[t][q];
+                    }
+                }
+            if (accept) Fk += dF;
+            if (live) ++k;
+        }
+
+        // ---- refill retired slots, stop when the tile is empty
+        const uint32_t rmask = (uint32_t)(__ballot(retire && h == 0) & 0xFFFFull);
+        if (retire) active = false;
+        refill(rmask);
+        if (__ballot(active) == 0) break;
+        adjoint();
+        n_adj += __popcll(__ballot(active && h == 0));
+    }
+    if (tid == 0) {
+        atomicAdd(&a.work[0], n_fwd);
+        atomicAdd(&a.work[1], n_adj);
+    }
+}
+
+
+
+template <int T, int KB, bool ALDS>
+hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s)
+{
+    const size_t lds = fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, ALDS);
+    auto kern = fista_mfma_kernel<T, KB, ALDS>;
+    static bool attr_done = false;  // per instantiation
+    if (!attr_done) {
+        hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr_done = true;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * a.waves, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t groups = (int64_t)per_cu * cus;
+    const int64_t need = (a.p + kTile - 1) / kTile;
+    if (groups > need) groups = need;
+    if (max_groups > 0 && groups > max_groups) groups = max_groups;
+    if (groups < 1) groups = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64 * a.waves), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace l1ls

@@ -29,7 +29,7 @@ struct StackConsts {
 struct FistaArgs {
     int n, l, l_pad, waves;
     int64_t p;
-    const float2 *A;          // packed: n x l_pad, zero padded columns
+    const float2 *A;          // packed: rows_pad_for(n) x l_pad, zero padded rows and columns
     const float2 *B;          // p x n
     const float *lambda;
     int64_t lambda_stride;
@@ -94,6 +94,7 @@ int slice_blocks_for(int l);   // KB
 int waves_for(int l);          // W
 int lpad_for(int l);           // 8 KB W
 int zblocks_for(int n);
+int rows_pad_for(int n);       // rows of the packed A: N rounded up to 16
 
 hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, double2 *gram,
                         StackConsts *consts, uint32_t *queue, unsigned long long *work,
@@ -122,6 +123,7 @@ hipError_t launch_unrolled_backward(int n, int l, int64_t p, const float2 *B, fl
                                     const float2 *dX, float2 *dB, float *dlambda, float *dxi,
                                     void *ws, hipStream_t st);
 size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds);
+size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds);
 bool fista_a_fits_lds(int n, int l_pad, int waves, int zb);
 
 }  // namespace l1ls
