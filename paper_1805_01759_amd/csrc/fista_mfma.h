@@ -380,8 +380,31 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
                 first = false;
             }
             l1 = S[1];
-            const bool fail = active && !retire && a.backtracking && (w2 > S[0] / (2.0f * alpha)) &&
-                              alpha > afloor;
+            float d2s = S[0];
+            bool jumped = false;
+            if (k == 1 && trial == 0 && active && !retire && a.backtracking && w2 > d2s / (2.0f * alpha) &&
+                alpha > afloor) {
+                // First iteration: y = x^0 = 0, so x-bar(alpha) = alpha S_lambda(-G_0) is linear
+                // in alpha and Eq. (15) reads alpha <= ||d||^2 / (2 ||A d||^2) at every alpha.
+                // The shrink sequence alpha0 C^i therefore ends where this one product
+                // says, and d, A d, ||x-bar||_1 scale with alpha: no further products.
+                const float rho = d2s / (2.0f * w2);
+                float an = alpha;
+                while (an > rho && an > afloor) an = fmaxf(a.c_alpha * an, afloor);
+                const float c = an / alpha;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    Wr[t] *= c;
+                    Wi[t] *= c;
+                }
+                w2 *= c * c;
+                d2s *= c * c;
+                l1 *= c;
+                alpha = an;
+                jumped = true;
+            }
+            const bool fail = active && !retire && !jumped && a.backtracking &&
+                              (w2 > d2s / (2.0f * alpha)) && alpha > afloor;
             if (__ballot(fail) == 0) break;
             if (fail) alpha = fmaxf(a.c_alpha * alpha, afloor);
         }

@@ -149,6 +149,21 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
                 ++n_fwd;
                 WAVE_SYNC();
                 if (!(a.backtracking && w2 > d2 / (2.0f * alpha) && alpha > afloor)) break;
+                if (k == 1 && trial == 0) {
+                    // First iteration: y = 0, so x-bar(alpha) = alpha S_lambda(-G_0) is linear in
+                    // alpha and Eq. (15) reads alpha <= ||d||^2 / (2 ||A d||^2) at every alpha:
+                    // jump to where the shrink sequence ends and scale d, A d, ||x-bar||_1.
+                    const float rho = d2 / (2.0f * w2);
+                    float an = alpha;
+                    while (an > rho && an > afloor) an = fmaxf(a.c_alpha * an, afloor);
+                    const float c = an / alpha;
+                    for (int j = lane; j < l; j += 64) D[j] = make_float2(D[j].x * c, D[j].y * c);
+                    for (int i = lane; i < n; i += 64) W[i] = make_float2(W[i].x * c, W[i].y * c);
+                    dl1 *= c;
+                    alpha = an;
+                    WAVE_SYNC();
+                    break;
+                }
                 alpha = fmaxf(a.c_alpha * alpha, afloor);
             }
             // monotone acceptance from differences
