@@ -30,24 +30,45 @@ constexpr int kMaxSupp = 16;          // Newton on at most 16 complex unknowns
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
 constexpr int kTri = kMaxM * (kMaxM + 1) / 2;
 
-__device__ __forceinline__ double wsum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wmax(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
 // value of v held by lane i (i uniform across the wave)
 __device__ __forceinline__ double lane_value(double v, int i)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
     return __hiloint2double(hi, lo);
+}
+
+// Wave reductions over DPP lane moves (register to register, no LDS round
+// trip): a row-wise inclusive scan with row_shr 1, 2, 4, 8 leaves each 16-lane
+// row's total in its lane 15; row_bcast 15 and 31 carry the row totals into
+// lane 63, which is broadcast.  Lanes whose source falls outside the row read
+// 0, so the max form is for non-negative values.  All 64 lanes must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wsum(double v)
+{
+    v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 -> rows 1, 3
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 -> rows 2, 3
+    return lane_value(v, 63);
+}
+__device__ __forceinline__ double wmax(double v)  // v >= 0
+{
+    v = fmax(v, dpp_move<0x111, 0xF>(v));
+    v = fmax(v, dpp_move<0x112, 0xF>(v));
+    v = fmax(v, dpp_move<0x114, 0xF>(v));
+    v = fmax(v, dpp_move<0x118, 0xF>(v));
+    v = fmax(v, dpp_move<0x142, 0xA>(v));
+    v = fmax(v, dpp_move<0x143, 0xC>(v));
+    return lane_value(v, 63);
 }
 __device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }  // k <= i
 
@@ -59,7 +80,7 @@ struct PolishShared {
     int8_t *sidx;       // l_pad: slot of bin m in the working set, or -1 (dynamic LDS)
     double H[kTri];     // packed lower triangle of the real Hessian / its Cholesky factor
     double2 z[kMaxSupp], zt[kMaxSupp];
-    double grd[kMaxM], dir[kMaxM];
+    double grd[kMaxM], dir[kMaxM], invd[kMaxM];
     int S[kMaxSupp];
     int cnt;
 };
@@ -74,12 +95,6 @@ __device__ __forceinline__ double2 ASat(const PolishShared &sh, int n, int t)
 {
     const float2 v = sh.AS[n * kMaxSupp + t];
     return make_double2(v.x, v.y);
-}
-
-// column t of the working set <- column m of A
-__device__ void stage_col(const PolishArgsDev &a, PolishShared &sh, int t, int m)
-{
-    for (int nn = threadIdx.x; nn < a.n; nn += 64) sh.AS[nn * kMaxSupp + t] = a.A[(size_t)nn * a.l_pad + m];
 }
 
 // r = A x0 - b for the starting point (its nonzero bins listed first)
@@ -117,14 +132,17 @@ __device__ void residual_start(const PolishArgsDev &a, PolishShared &sh, const f
     __syncthreads();
 }
 
-// phi(z) on the working set, r <- A_S z - b; returns phi (all lanes)
-__device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, const float2 *b,
+// phi(z) on the working set, r <- A_S z - b; returns phi (all lanes).  b0, b1:
+// the data b of rows lane and lane + 64, held in registers.
+__device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, float2 b0, float2 b1,
                               const double2 *z, int s, double lam)
 {
     const int lane = threadIdx.x;
     double acc = 0.0;
-    for (int nn = lane; nn < a.n; nn += 64) {
-        double rr = -(double)b[nn].x, ri = -(double)b[nn].y;
+    for (int nn = lane, i = 0; nn < a.n; nn += 64, ++i) {
+        const float2 bb = i == 0 ? b0 : b1;
+        double rr = -(double)bb.x, ri = -(double)bb.y;
+#pragma unroll 4
         for (int t = 0; t < s; ++t) {
             const double2 av = ASat(sh, nn, t);
             const double2 zv = z[t];
@@ -134,25 +152,36 @@ __device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, const fl
         sh.r[nn] = make_double2(rr, ri);
         acc += rr * rr + ri * ri;
     }
-    double l1 = 0.0;
-    for (int t = lane; t < s; t += 64) l1 += sqrt(z[t].x * z[t].x + z[t].y * z[t].y);
-    const double out = wsum(acc) + lam * wsum(l1);
+    for (int t = lane; t < s; t += 64) acc += lam * sqrt(z[t].x * z[t].x + z[t].y * z[t].y);
+    const double out = wsum(acc);
     __syncthreads();
     return out;
 }
 
 // Full FP64 pass at the current point (sh.r its residual): natural KKT
 // residual, objective, and the worst off-support violator of |g| <= lambda.
-// START: the point is the starting iterate in sh.best; else it is z on the
-// working set (sh.sidx).
+// START: the point is the starting iterate in sh.best (its nonzero bins listed
+// in sh.nzl[0..nnz)); else it is z on the working set (sh.sidx, s entries).
+// Magnitudes are compared squared; the prox scale (a square root and a
+// division) is formed only on lanes whose |v| passes the threshold.
 template <bool START>
-__device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, double lam, double lf,
-                          double &F, double &kk, int &vidx)
+__device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, int s, int nnz, double lam,
+                          double lf, double inv_lf, double &F, double &kk, int &vidx)
 {
     const int lane = threadIdx.x;
     double acc = 0.0, l1 = 0.0, km = 0.0, vbest = 0.0;
     vidx = -1;
     for (int nn = lane; nn < a.n; nn += 64) acc += sh.r[nn].x * sh.r[nn].x + sh.r[nn].y * sh.r[nn].y;
+    if (START) {
+        for (int q = lane; q < nnz; q += 64) {
+            const float2 v = sh.best[sh.nzl[q]];
+            l1 += sqrt((double)v.x * v.x + (double)v.y * v.y);
+        }
+    } else {
+        for (int t = lane; t < s; t += 64) l1 += sqrt(sh.z[t].x * sh.z[t].x + sh.z[t].y * sh.z[t].y);
+    }
+    const double tau = lam * inv_lf, tau2 = tau * tau;
+    const double lv = lam * (1.0 + 1e-12), lv2 = lv * lv;
     for (int m = lane; m < a.l; m += 64) {
         double xr, xi;
         if (START) {
@@ -165,63 +194,90 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, double lam, 
             xr = v.x;
             xi = v.y;
         }
-        l1 += sqrt(xr * xr + xi * xi);
+        // g_m = 2 a_m^H r, the column read eight rows at a time (loads in flight together)
         double gr = 0.0, gi = 0.0;
-        for (int nn = 0; nn < a.n; ++nn) {
-            const double2 av = Aat(a, nn, m), rv = sh.r[nn];
-            gr += av.x * rv.x + av.y * rv.y;
-            gi += av.x * rv.y - av.y * rv.x;
+        const float2 *col = a.A + m;
+        int nn = 0;
+        for (; nn + 8 <= a.n; nn += 8) {
+            float2 af[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) af[u] = col[(size_t)(nn + u) * a.l_pad];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double2 rv = sh.r[nn + u];
+                gr += af[u].x * rv.x + af[u].y * rv.y;
+                gi += af[u].x * rv.y - af[u].y * rv.x;
+            }
+        }
+        for (; nn < a.n; ++nn) {
+            const float2 af = col[(size_t)nn * a.l_pad];
+            const double2 rv = sh.r[nn];
+            gr += af.x * rv.x + af.y * rv.y;
+            gi += af.x * rv.y - af.y * rv.x;
         }
         gr *= 2.0;
         gi *= 2.0;
-        const double vr = xr - gr / lf, vi = xi - gi / lf;
-        const double mag = sqrt(vr * vr + vi * vi), tau = lam / lf;
-        const double sc = mag > tau ? 1.0 - tau / mag : 0.0;
-        const double er = xr - vr * sc, ei = xi - vi * sc;
-        km = fmax(km, sqrt(er * er + ei * ei));
-        const double gm = sqrt(gr * gr + gi * gi);
-        if (xr == 0.0 && xi == 0.0 && gm > lam * (1.0 + 1e-12) && gm > vbest) {
-            vbest = gm;
+        const double vr = xr - gr * inv_lf, vi = xi - gi * inv_lf;
+        const double m2 = vr * vr + vi * vi;
+        double er = xr, ei = xi;  // x - prox(v), prox(v) = 0 when |v| <= tau
+        if (m2 > tau2) {
+            const double sc = 1.0 - tau / sqrt(m2);
+            er = xr - vr * sc;
+            ei = xi - vi * sc;
+        }
+        km = fmax(km, er * er + ei * ei);
+        const double gm2 = gr * gr + gi * gi;
+        if (xr == 0.0 && xi == 0.0 && gm2 > lv2 && gm2 > vbest) {
+            vbest = gm2;
             vidx = m;
         }
     }
-    F = wsum(acc) + lam * wsum(l1);
-    kk = wmax(km) * lf / lam;
-    for (int o = 32; o > 0; o >>= 1) {  // wave argmax of the violation (ties: lowest index)
-        const double ov = __shfl_xor(vbest, o, 64);
-        const int oi = __shfl_xor(vidx, o, 64);
-        if (ov > vbest || (ov == vbest && oi >= 0 && (vidx < 0 || oi < vidx))) {
-            vbest = ov;
-            vidx = oi;
-        }
+    F = wsum(acc + lam * l1);
+    kk = sqrt(wmax(km)) * lf / lam;
+    // wave argmax of the violation (ties: lowest bin)
+    const double vmax = wmax(vbest);
+    uint64_t cand = __ballot(vmax > 0.0 && vbest == vmax);
+    int best = -1;
+    while (cand) {
+        const int ln = __ffsll((unsigned long long)cand) - 1;
+        cand &= cand - 1;
+        const int m = __builtin_amdgcn_readlane(vidx, ln);
+        if (best < 0 || m < best) best = m;
     }
+    vidx = best;
 }
 
 // Packed lower triangle of 2 realify(A_S^H A_S) + lambda blkdiag((I - u u^T)/|z|) + mu I.
-// Lanes are split into 64/E groups over the rows of A_S when the s x s entries
-// fit E = 16 lanes; the group partial sums are combined with shuffles.
+// G = A_S^H A_S is Hermitian, so only its entries t >= u are formed; lanes are
+// split into 64/E groups over the rows of A_S when those entries fit E lanes,
+// and the group partial sums are combined with shuffles.
 __device__ void build_hessian(const PolishArgsDev &a, PolishShared &sh, int s, double lam, double mu)
 {
     const int lane = threadIdx.x;
-    const int ne = s * s;
-    const bool grouped = ne <= 16;
-    const int E = grouped ? 16 : 64, G = grouped ? 4 : 1;
+    const int ne = s * (s + 1) / 2;
+    const int E = ne <= 16 ? 16 : (ne <= 32 ? 32 : 64), G = 64 / E;
     const int q = lane / E;
     for (int e0 = 0; e0 < ne; e0 += E) {
         const int e = e0 + lane % E;
         const bool act = e < ne;
-        const int t = act ? e / s : 0, u = act ? e % s : 0;
+        int t = 0;
+        if (act)
+            while ((t + 1) * (t + 2) / 2 <= e) ++t;
+        const int u = act ? e - t * (t + 1) / 2 : 0;
         double gr = 0.0, gi = 0.0;
         if (act) {
+#pragma unroll 4
             for (int nn = q; nn < a.n; nn += G) {
                 const double2 p1 = ASat(sh, nn, t), p2 = ASat(sh, nn, u);
                 gr += p1.x * p2.x + p1.y * p2.y;  // conj(p1) p2
                 gi += p1.x * p2.y - p1.y * p2.x;
             }
         }
-        if (grouped) {
+        if (G >= 4) {
             gr += __shfl_xor(gr, 16, 64);
             gi += __shfl_xor(gi, 16, 64);
+        }
+        if (G >= 2) {
             gr += __shfl_xor(gr, 32, 64);
             gi += __shfl_xor(gi, 32, 64);
         }
@@ -229,67 +285,74 @@ __device__ void build_hessian(const PolishArgsDev &a, PolishShared &sh, int s, d
             double h00 = 2.0 * gr, h11 = 2.0 * gr, h10 = 2.0 * gi;
             if (t == u) {
                 const double2 zv = sh.z[t];
-                const double az = sqrt(zv.x * zv.x + zv.y * zv.y);
-                const double ur = zv.x / az, ui = zv.y / az;
-                h00 += lam * (1.0 - ur * ur) / az + mu;
-                h11 += lam * (1.0 - ui * ui) / az + mu;
-                h10 -= lam * ur * ui / az;
+                const double az = sqrt(zv.x * zv.x + zv.y * zv.y), iz = 1.0 / az;
+                const double ur = zv.x * iz, ui = zv.y * iz;
+                h00 += lam * (1.0 - ur * ur) * iz + mu;
+                h11 += lam * (1.0 - ui * ui) * iz + mu;
+                h10 -= lam * ur * ui * iz;
+            } else {
+                sh.H[tri(u + s, t)] = -h10;  // 2 Im G[u][t] = -2 Im G[t][u]
             }
-            if (t >= u) {
-                sh.H[tri(t, u)] = h00;
-                sh.H[tri(t + s, u + s)] = h11;
-            }
+            sh.H[tri(t, u)] = h00;
+            sh.H[tri(t + s, u + s)] = h11;
             sh.H[tri(t + s, u)] = h10;
         }
     }
     __syncthreads();
 }
 
-// In-place Cholesky of the packed matrix of order m2; false if not positive definite.
+// In-place Cholesky of the packed matrix of order m2 (strict lower part of the
+// factor in sh.H, reciprocal of its diagonal in sh.invd); false if not positive definite.
 __device__ bool cholesky(PolishShared &sh, int m2)
 {
     const int lane = threadIdx.x;
     bool good = true;
     for (int jj = 0; jj < m2; ++jj) {
         double djj = sh.H[tri(jj, jj)];
+#pragma unroll 4
         for (int k = 0; k < jj; ++k) djj -= sh.H[tri(jj, k)] * sh.H[tri(jj, k)];
         if (!(djj > 0.0)) {
             good = false;
             break;
         }
-        djj = sqrt(djj);
+        // 1/sqrt(djj): hardware estimate refined by two Newton-Raphson steps
+        double inv = __builtin_amdgcn_rsq(djj);
+        inv = inv * fma(-0.5 * djj, inv * inv, 1.5);
+        inv = inv * fma(-0.5 * djj, inv * inv, 1.5);
         for (int i = jj + 1 + lane; i < m2; i += 64) {
             double t = sh.H[tri(i, jj)];
+#pragma unroll 4
             for (int k = 0; k < jj; ++k) t -= sh.H[tri(i, k)] * sh.H[tri(jj, k)];
-            sh.H[tri(i, jj)] = t / djj;
+            sh.H[tri(i, jj)] = t * inv;
         }
+        if (lane == 0) sh.invd[jj] = inv;
         __syncthreads();
-        if (lane == 0) sh.H[tri(jj, jj)] = djj;
     }
     __syncthreads();
     return good;
 }
 
-// Solve L L^T d = -grd with the factor in sh.H; lane k ends holding d_k
+// Solve L L^T d = -grd with the factor in sh.H / sh.invd; lane k ends holding d_k
 // (column-oriented substitutions, one broadcast per column).
 __device__ double newton_dir(const PolishShared &sh, int m2)
 {
     const int lane = threadIdx.x;
     double v = lane < m2 ? -sh.grd[lane] : 0.0;
+    const double invl = lane < m2 ? sh.invd[lane] : 0.0;
     for (int i = 0; i < m2; ++i) {
-        const double yi = lane_value(v, i) / sh.H[tri(i, i)];
+        const double yi = lane_value(v, i) * lane_value(invl, i);
         if (lane == i) v = yi;
         else if (lane > i && lane < m2) v -= sh.H[tri(lane, i)] * yi;
     }
     for (int i = m2 - 1; i >= 0; --i) {
-        const double di = lane_value(v, i) / sh.H[tri(i, i)];
+        const double di = lane_value(v, i) * lane_value(invl, i);
         if (lane == i) v = di;
         else if (lane < i) v -= sh.H[tri(i, lane)] * di;
     }
     return v;
 }
 
-__global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) polish_kernel(const PolishArgsDev a)
 {
     __shared__ PolishShared sh;
     extern __shared__ __align__(16) unsigned char dyn[];
@@ -308,6 +371,7 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
     }
     __syncthreads();
     const double lf = a.consts->lf;
+    const double inv_lf = 1.0 / lf;
     const double gstop = a.mode == 2 ? 1e-13 : 1e-3 * (double)a.tol;
     const double kstop = a.mode == 2 ? 1e-10 : 1e-2 * (double)a.tol;
     const uint32_t count = *a.count;
@@ -317,6 +381,8 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
         if (!(lam_f > 0.0f) || !isfinite(lam_f)) continue;
         const double lam = lam_f;
         const float2 *b = a.B + (size_t)p * a.n;
+        const float2 b0 = lane < a.n ? b[lane] : make_float2(0.0f, 0.0f);
+        const float2 b1 = lane + 64 < a.n ? b[lane + 64] : make_float2(0.0f, 0.0f);
         float2 *xo = a.X + (size_t)p * a.l;
         for (int m = lane; m < a.l_pad; m += 64) {
             sh.best[m] = m < a.l ? xo[m] : make_float2(0.0f, 0.0f);
@@ -327,7 +393,7 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
         residual_start(a, sh, b);
         double fbest, kk0;
         int vdummy;
-        full_pass<true>(a, sh, lam, lf, fbest, kk0, vdummy);
+        full_pass<true>(a, sh, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
         __syncthreads();
         if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
         // -- working set: the local maxima of |x| (FISTA spreads one scatterer
@@ -379,12 +445,15 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
             __syncthreads();
         }
         int s = sh.cnt;
-        for (int t = 0; t < s; ++t) stage_col(a, sh, t, sh.S[t]);
+        for (int e = lane; e < a.n * s; e += 64) {  // all columns of the working set at once
+            const int nn = e / s, t = e % s;
+            sh.AS[nn * kMaxSupp + t] = a.A[(size_t)nn * a.l_pad + sh.S[t]];
+        }
         __syncthreads();
         for (int round = 0; round < a.rounds; ++round) {
             for (int it = 0; it < 50 && s > 0; ++it) {
                 const int m2 = 2 * s;
-                const double ph = phi_support(a, sh, b, sh.z, s, lam);
+                const double ph = phi_support(a, sh, b0, b1, sh.z, s, lam);
                 // gradient of phi on the working set (real pairs); 4 lane groups
                 // over the rows of A_S
                 double gmax = 0.0;
@@ -392,6 +461,7 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
                     const int t = lane & 15, q = lane >> 4;
                     double gr = 0.0, gi = 0.0;
                     if (t < s) {
+#pragma unroll 4
                         for (int nn = q; nn < a.n; nn += 4) {
                             const double2 av = ASat(sh, nn, t), rv = sh.r[nn];
                             gr += av.x * rv.x + av.y * rv.y;
@@ -430,19 +500,25 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
                 if (lane < m2) sh.dir[lane] = dv;
                 __syncthreads();
                 // the coordinate the step turns round most leaves the working set
-                if (lane == 0) {
-                    int drop = -1;
-                    double worst = 0.0;
-                    for (int t = 0; t < s; ++t) {
-                        const double2 zv = sh.z[t];
-                        const double nr = zv.x + sh.dir[t], ni = zv.y + sh.dir[t + s];
-                        const double c = (zv.x * nr + zv.y * ni) / (zv.x * zv.x + zv.y * zv.y);
-                        if (c <= 0.0 && (drop < 0 || c < worst)) { drop = t; worst = c; }
-                    }
-                    sh.cnt = drop;
+                // (lanes over coordinates; ties: the lowest slot)
+                double cq = 1.0;
+                if (lane < s) {
+                    const double2 zv = sh.z[lane];
+                    const double nr = zv.x + sh.dir[lane], ni = zv.y + sh.dir[lane + s];
+                    cq = (zv.x * nr + zv.y * ni) / (zv.x * zv.x + zv.y * zv.y);
                 }
-                __syncthreads();
-                const int drop = sh.cnt;
+                uint64_t cand = __ballot(lane < s && cq <= 0.0);
+                int drop = -1;
+                double worst = 0.0;
+                while (cand) {
+                    const int t = __ffsll((unsigned long long)cand) - 1;
+                    cand &= cand - 1;
+                    const double c = lane_value(cq, t);
+                    if (drop < 0 || c < worst) {
+                        drop = t;
+                        worst = c;
+                    }
+                }
                 if (drop >= 0) {
                     // remove column `drop` from the working set (lanes over rows of A_S)
                     for (int nn = lane; nn < a.n; nn += 64)
@@ -472,7 +548,7 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
                     for (int t = lane; t < s; t += 64)
                         sh.zt[t] = make_double2(sh.z[t].x + step * sh.dir[t], sh.z[t].y + step * sh.dir[t + s]);
                     __syncthreads();
-                    const double pn = phi_support(a, sh, b, sh.zt, s, lam);
+                    const double pn = phi_support(a, sh, b0, b1, sh.zt, s, lam);
                     if (pn <= ph + 1e-4 * step * slope) { acc = true; break; }
                     step *= 0.5;
                 }
@@ -483,10 +559,10 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
             // the working set as the current point; its residual
             for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = (int8_t)t;
             __syncthreads();
-            phi_support(a, sh, b, sh.z, s, lam);
+            phi_support(a, sh, b0, b1, sh.z, s, lam);
             double F, kk;
             int vidx;
-            full_pass<false>(a, sh, lam, lf, F, kk, vidx);
+            full_pass<false>(a, sh, s, 0, lam, lf, inv_lf, F, kk, vidx);
             if (F <= fbest) {
                 fbest = F;
                 for (int m = lane; m < a.l_pad; m += 64) {
@@ -500,23 +576,28 @@ __global__ void __launch_bounds__(64) polish_kernel(const PolishArgsDev a)
             if (kk <= kstop) break;
             if (vidx < 0 || s >= kMaxSupp) break;
             // the worst violator enters at its exact coordinate minimiser
-            stage_col(a, sh, s, vidx);
+            // (lanes over rows: the column is staged and a^H r, ||a||^2 formed at once)
+            double gr = 0.0, gi = 0.0, cn = 0.0;
+            for (int nn = lane; nn < a.n; nn += 64) {
+                const float2 af = a.A[(size_t)nn * a.l_pad + vidx];
+                sh.AS[nn * kMaxSupp + s] = af;
+                const double2 rv = sh.r[nn];
+                gr += af.x * rv.x + af.y * rv.y;
+                gi += af.x * rv.y - af.y * rv.x;
+                cn += (double)af.x * af.x + (double)af.y * af.y;
+            }
+            gr = wsum(gr);
+            gi = wsum(gi);
+            cn = wsum(cn);
+            // argmin_z |a z + r|^2 + lambda |z| = -S_{lambda/2}(a^H r) / ||a||^2
+            const double mag = sqrt(gr * gr + gi * gi), tau = 0.5 * lam;
+            const double sc = mag > tau ? (1.0 - tau / mag) / cn : 0.0;
             if (lane == 0) {
-                double gr = 0.0, gi = 0.0, cn = 0.0;
-                for (int nn = 0; nn < a.n; ++nn) {
-                    const double2 av = Aat(a, nn, vidx), rv = sh.r[nn];
-                    gr += av.x * rv.x + av.y * rv.y;
-                    gi += av.x * rv.y - av.y * rv.x;
-                    cn += av.x * av.x + av.y * av.y;
-                }
-                // argmin_z |a z + r|^2 + lambda |z| = -S_{lambda/2}(a^H r) / ||a||^2
-                const double mag = sqrt(gr * gr + gi * gi), tau = 0.5 * lam;
-                const double sc = mag > tau ? (1.0 - tau / mag) / cn : 0.0;
                 sh.S[s] = vidx;
                 sh.z[s] = make_double2(-gr * sc, -gi * sc);
             }
             __syncthreads();
-            if (sh.z[s].x == 0.0 && sh.z[s].y == 0.0) break;
+            if (sc == 0.0) break;
             ++s;
         }
         for (int m = lane; m < a.l; m += 64) xo[m] = sh.best[m];
