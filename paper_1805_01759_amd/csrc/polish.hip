@@ -352,7 +352,64 @@ __device__ double newton_dir(const PolishShared &sh, int m2)
     return v;
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) polish_kernel(const PolishArgsDev a)
+// The Newton system H d = -grd of order m2 <= NS solved in registers: lane
+// i < NS holds row i of H (the identity pads rows and columns m2..NS-1), a
+// right-looking Cholesky broadcasts each column with readlane, and both
+// substitutions run on the same registers: no LDS traffic or barrier inside.
+// Returns false (wave-uniform) if H is not positive definite; lane i ends
+// holding d_i.
+template <int NS>
+__device__ bool newton_regs(const PolishShared &sh, int m2, double &d)
+{
+    const int lane = threadIdx.x;
+    double row[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (lane < m2 && k < m2)
+            row[k] = k <= lane ? sh.H[tri(lane, k)] : sh.H[tri(k, lane)];
+        else
+            row[k] = k == lane ? 1.0 : 0.0;
+    }
+    double invl = 0.0;  // lane j: 1 / L_jj
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const double piv = lane_value(row[j], j);
+        if (!(piv > 0.0)) return false;
+        // 1/sqrt(piv): hardware estimate refined by two Newton-Raphson steps
+        double iv = __builtin_amdgcn_rsq(piv);
+        iv = iv * fma(-0.5 * piv, iv * iv, 1.5);
+        iv = iv * fma(-0.5 * piv, iv * iv, 1.5);
+        if (lane == j) invl = iv;
+        const double lj = row[j] * iv;  // lane i >= j: L_ij
+        row[j] = lj;
+        const double act = lane > j ? lj : 0.0;
+#pragma unroll
+        for (int k = j + 1; k < NS; ++k) row[k] -= act * lane_value(lj, k);  // - L_ij L_kj
+    }
+    // L y = -grd (lane i > j holds L_ij in row[j])
+    double v = lane < m2 ? -sh.grd[lane] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const double yj = lane_value(v, j) * lane_value(invl, j);
+        if (lane == j) v = yj;
+        else if (lane > j) v -= row[j] * yj;
+    }
+    // L^T d = y (L_ji, i < j, is lane j's row[i], broadcast)
+#pragma unroll
+    for (int j = NS - 1; j >= 0; --j) {
+        const double dj = lane_value(v, j) * lane_value(invl, j);
+        if (lane == j) v = dj;
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            const double lji = lane_value(row[i], j);
+            if (lane == i) v -= lji * dj;
+        }
+    }
+    d = v;
+    return true;
+}
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) polish_kernel(const PolishArgsDev a)
 {
     __shared__ PolishShared sh;
     extern __shared__ __align__(16) unsigned char dyn[];
@@ -488,15 +545,19 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) po
                 __syncthreads();
                 if (gmax <= gstop * lam) break;
                 // Newton direction; shifted retries while the Hessian is not PD
-                double mu = 0.0;
+                double mu = 0.0, dv = 0.0;
                 bool ok = false;
                 for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
                     build_hessian(a, sh, s, lam, mu);
-                    ok = cholesky(sh, m2);
+                    if (m2 <= 8) {
+                        ok = newton_regs<8>(sh, m2, dv);
+                    } else {
+                        ok = cholesky(sh, m2);
+                        if (ok) dv = newton_dir(sh, m2);
+                    }
                     mu = mu == 0.0 ? 1e-14 * lf : mu * 100.0;
                 }
                 if (!ok) break;
-                const double dv = newton_dir(sh, m2);
                 if (lane < m2) sh.dir[lane] = dv;
                 __syncthreads();
                 // the coordinate the step turns round most leaves the working set
