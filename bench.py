@@ -32,19 +32,30 @@ WORKLOADS = {
 }
 
 
-def kernel_sha() -> str:
+# sources of each timed kernel; a traffic record is used only while they are unchanged
+KERNEL_SOURCES = {
+    "fista_mfma_kernel": ("fista_mfma.h", "fista.hip"),
+    "fista_kernel": ("fista_impl.h", "fista.hip"),
+    "polish_kernel": ("polish.hip",),
+}
+PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
+
+
+def kernel_sha(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in ("fista_mfma.h", "fista_impl.h", "fista.hip"):
+    for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(HERE, "paper_1805_01759_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    path = os.path.join(HERE, "profiles", f"fista_{workload}_traffic.json")
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record of this kernel and workload, or None once the kernel has changed."""
+    path = os.path.join(HERE, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_sha") != kernel_sha():
+    if rec.get("kernel_sha") != kernel_sha(kernel):
         return None  # counters were taken on a different kernel
     return rec.get("traffic_bytes_per_launch")
 
@@ -217,7 +228,8 @@ def main():
         api.solve(Ad, Bd, ld, out=X, workspace=ws, **opts)
     torch.cuda.synchronize()
     api.timing_enable(True)
-    api.timing_read()
+    for kc in ("iteration", "refine", "certify"):
+        api.timing_read(kc)
     diags = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -226,14 +238,29 @@ def main():
         diags.append(d["status"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    k_ms, k_launches = api.timing_read()
+    kt = {kc: api.timing_read(kc) for kc in ("iteration", "refine", "certify")}
     api.timing_enable(False)
     solved = sum(int(((s & 1) != 0).sum().item()) for s in diags)
-    fwd, adj, npol = api.solve_counters(n, l, p, d)
-    flops = (fwd + adj) * 8.0 * n * l          # algorithmic flops of one iteration launch
-    k_avg_s = (k_ms / max(k_launches, 1)) / 1e3
-    achieved = flops / k_avg_s
-    traffic = load_traffic(args.workload)
+    fwd, adj, npol, pflops = api.solve_counters(n, l, p, d)
+    avg_s = {kc: (ms / max(c, 1)) / 1e3 for kc, (ms, c) in kt.items()}
+    # iteration kernel: algorithmic flops = (forward + adjoint products) x 8 N L
+    it_kernel = "fista_mfma_kernel" if args.precision == "fp32" else "fista_kernel"
+    it_flops = (fwd + adj) * 8.0 * n * l
+    it_ach = it_flops / avg_s["iteration"]
+    roof_it = {"bound": "mfma", "achieved": it_ach / 1e12, "peak": PEAK[args.precision] / 1e12,
+               "unit": "TFLOP/s", "frac": it_ach / PEAK[args.precision],
+               "traffic": load_traffic(it_kernel, args.workload), "kernel": it_kernel,
+               "kernel_ms": avg_s["iteration"] * 1e3, "flops_per_launch": it_flops}
+    roof = roof_it
+    if args.polish and avg_s["refine"] > 0:
+        # FP64 refinement: plain FP64 VALU arithmetic, flops counted by the kernel
+        rf_ach = pflops / avg_s["refine"]
+        roof_rf = {"bound": "alu", "achieved": rf_ach / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                   "unit": "TFLOP/s", "frac": rf_ach / PEAK_FP64_VALU,
+                   "traffic": load_traffic("polish_kernel", args.workload), "kernel": "polish_kernel",
+                   "kernel_ms": avg_s["refine"] * 1e3, "flops_per_launch": float(pflops)}
+        if avg_s["refine"] > avg_s["iteration"]:
+            roof = roof_rf
     rec = {
         "metric": METRIC,
         "value": solved / dt,
@@ -249,14 +276,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc if not args.pixels else desc + f" (first {p} pixels)", "n": n, "l": l, "pixels": p, "max_iter": args.max_iter,
                    "tol": 1e-4, "precision": args.precision, "polish_after": args.polish_after,
-                   "solved_fraction": solved / (p * args.steps), "pixels_refined_fp64": npol},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
-                     "traffic": traffic,
-                     "kernel": "fista_mfma_kernel" if args.precision == "fp32" else "fista_kernel",
-                     "kernel_ms": k_avg_s * 1e3,
-                     "flops_per_launch": flops},
+                   "solved_fraction": solved / (p * args.steps), "pixels_refined_fp64": npol,
+                   "kernel_ms": {kc: avg_s[kc] * 1e3 for kc in avg_s}},
+        # dominant kernel by event-timed duration
+        "roofline": roof,
     }
+    if roof is not roof_it:
+        rec["roofline_iteration"] = roof_it
+    elif args.polish and avg_s["refine"] > 0:
+        rec["roofline_refine"] = roof_rf
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(A32, B32, l32, min(args.cpu_sample, p), args.max_iter, 1e-4)
     print(json.dumps(rec), flush=True)

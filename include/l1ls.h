@@ -183,19 +183,33 @@ l1ls_status l1ls_unrolled_backward(int32_t n, int32_t l, int64_t p, const float 
 
 /* Work counters of the last l1ls_solve that used `workspace` (synchronises
  * `stream`): out[0] pixel forward products A d, out[1] pixel adjoint products
- * A^H r (each 8 N L real flops), out[2] pixels handed to the FP64 refinement. */
+ * A^H r (each 8 N L real flops), out[2] pixels handed to the FP64 refinement,
+ * out[3] FP64 flops of the refinement's algorithm (full gradient passes
+ * 8 N L each, working-set residuals and gradients 8 N |S|, Gram entries
+ * 8 N, factorisations (2|S|)^3/3, substitutions 2 (2|S|)^2), counted by the
+ * kernel as it runs.  `out` holds 4 entries. */
 l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *workspace,
-                                hipStream_t stream, uint64_t out[3]);
+                                hipStream_t stream, uint64_t out[4]);
 
 /* Name of a status code; detail of the last error on the calling thread. */
 const char *l1ls_status_string(l1ls_status s);
 const char *l1ls_last_error(void);
 
-/* Average duration in milliseconds of the main iteration kernel over the
- * launches made since the last reset, measured with HIP events on the stream
- * it was launched on (only when timing is enabled). */
+/* Kernel classes of a solve, for event timing. */
+typedef enum {
+    L1LS_KERNEL_ITERATION = 0, /* the accelerated proximal-gradient iteration */
+    L1LS_KERNEL_REFINE = 1,    /* the FP64 refinement */
+    L1LS_KERNEL_CERTIFY = 2    /* the FP64 KKT certificate */
+} l1ls_kernel_class;
+
+/* Event timing (opt-in, for measurement): while enabled, every kernel launch of
+ * l1ls_solve is bracketed by HIP events on its stream.  l1ls_timing_read_kernel
+ * returns the total milliseconds and the number of launches of one kernel
+ * class since its last read (and resets that class); -1 for an unknown class.
+ * l1ls_timing_read is the same for L1LS_KERNEL_ITERATION. */
 void l1ls_timing_enable(int32_t on);
 int32_t l1ls_timing_read(double *total_ms, int32_t *launches);
+int32_t l1ls_timing_read_kernel(int32_t kernel_class, double *total_ms, int32_t *launches);
 
 #ifdef __cplusplus
 }

@@ -26,8 +26,11 @@ EXPORTS = [
     "l1ls_plan_describe",
     "l1ls_unrolled_tape_size", "l1ls_unrolled_backward_ws_size", "l1ls_unrolled_forward",
     "l1ls_unrolled_backward", "l1ls_status_string", "l1ls_last_error",
-    "l1ls_timing_enable", "l1ls_timing_read", "l1ls_solve_counters",
+    "l1ls_timing_enable", "l1ls_timing_read", "l1ls_timing_read_kernel", "l1ls_solve_counters",
 ]
+
+# kernel classes for l1ls_timing_read_kernel
+KERNEL_ITERATION, KERNEL_REFINE, KERNEL_CERTIFY = 0, 1, 2
 
 
 class Options(ctypes.Structure):
@@ -101,7 +104,9 @@ def load() -> ctypes.CDLL:
     L.l1ls_timing_enable.restype = None
     L.l1ls_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
     L.l1ls_timing_read.restype = I32
-    L.l1ls_solve_counters.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(ctypes.c_uint64 * 3)]
+    L.l1ls_timing_read_kernel.argtypes = [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
+    L.l1ls_timing_read_kernel.restype = I32
+    L.l1ls_solve_counters.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(ctypes.c_uint64 * 4)]
     L.l1ls_solve_counters.restype = st
     _lib = L
     return L

@@ -115,22 +115,26 @@ def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = N
 
 
 def solve_counters(n: int, l: int, p: int, diag, stream=None):
-    """(forward products, adjoint products, pixels refined) of the solve that made `diag`."""
-    out = (ctypes.c_uint64 * 3)()
+    """(forward products, adjoint products, pixels refined, refinement FP64 flops)
+    of the solve that made `diag`."""
+    out = (ctypes.c_uint64 * 4)()
     _lib.check(_lib.load().l1ls_solve_counters(n, l, p, _ptr(diag["_ws"]), _stream(stream),
                                                ctypes.byref(out)), "l1ls_solve_counters")
-    return int(out[0]), int(out[1]), int(out[2])
+    return int(out[0]), int(out[1]), int(out[2]), int(out[3])
 
 
 def timing_enable(on: bool = True) -> None:
     _lib.load().l1ls_timing_enable(int(on))
 
 
-def timing_read():
-    """(total milliseconds, launches) of the iteration kernel since the last read."""
+def timing_read(kernel: str = "iteration"):
+    """(total milliseconds, launches) of one kernel class of l1ls_solve since its
+    last read: "iteration", "refine" or "certify"."""
+    cls = {"iteration": _lib.KERNEL_ITERATION, "refine": _lib.KERNEL_REFINE,
+           "certify": _lib.KERNEL_CERTIFY}[kernel]
     tot = ctypes.c_double(0.0)
     cnt = ctypes.c_int32(0)
-    _lib.load().l1ls_timing_read(ctypes.byref(tot), ctypes.byref(cnt))
+    _lib.load().l1ls_timing_read_kernel(cls, ctypes.byref(tot), ctypes.byref(cnt))
     return tot.value, cnt.value
 
 

@@ -50,7 +50,7 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     w.queue = off;
     off = align_up(off + 4 * sizeof(uint32_t), 256);
     w.work = off;
-    off = align_up(off + 2 * sizeof(unsigned long long), 256);
+    off = align_up(off + 4 * sizeof(unsigned long long), 256);
     w.status = off;
     off = align_up(off + (size_t)p * sizeof(uint32_t), 256);
     w.iters = off;
@@ -107,15 +107,17 @@ static l1ls_status check_shape(int32_t n, int32_t l, int64_t p)
 
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Event timing of the persistent kernel (opt-in, for measurement).
+// Event timing of the solve's kernels (opt-in, for measurement), one list per
+// kernel class (l1ls_kernel_class).
 static std::mutex g_tmu;
 static bool g_timing = false;
-static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events[3];
 
 struct TimedLaunch {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t s;
-    explicit TimedLaunch(hipStream_t st) : s(st)
+    int cls;
+    TimedLaunch(hipStream_t st, int c) : s(st), cls(c)
     {
         std::lock_guard<std::mutex> g(g_tmu);
         if (!g_timing) return;
@@ -128,7 +130,7 @@ struct TimedLaunch {
         if (!e0) return;
         hipEventRecord(e1, s);
         std::lock_guard<std::mutex> g(g_tmu);
-        g_events.push_back({e0, e1});
+        g_events[cls].push_back({e0, e1});
     }
 };
 
@@ -197,7 +199,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     if (choice == kMfma && !mfma_supports(n, l))
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
     {
-        TimedLaunch t(s);
+        TimedLaunch t(s, L1LS_KERNEL_ITERATION);
         e = choice == kMfma ? launch_fista(fa, opt->precision, 0, s) : launch_fista_wave(fa, s);
     }
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
@@ -219,9 +221,11 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         pa.rounds = 64;
         pa.mode = opt->fp64_polish;
         pa.tol = opt->tol;
+        pa.work = work;
         int dev = 0, cus = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        TimedLaunch t(s, L1LS_KERNEL_REFINE);
         e = launch_polish(pa, cus * 8, s);
         if (e != hipSuccess) return fail(L1LS_ERR_HIP, "polish launch: %s", hipGetErrorString(e));
     }
@@ -246,7 +250,10 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     ca.objective = diag ? diag->objective : nullptr;
     ca.status = diag ? diag->status : nullptr;
     ca.nnz = diag ? diag->nnz : nullptr;
-    e = launch_certify(ca, s);
+    {
+        TimedLaunch t(s, L1LS_KERNEL_CERTIFY);
+        e = launch_certify(ca, s);
+    }
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "certify launch: %s", hipGetErrorString(e));
     return L1LS_OK;
 }
@@ -311,11 +318,11 @@ const char *l1ls_status_string(l1ls_status s)
 const char *l1ls_last_error(void) { return g_err; }
 
 l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *workspace,
-                                hipStream_t stream, uint64_t out[3])
+                                hipStream_t stream, uint64_t out[4])
 {
     if (!workspace || !out) return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
     const StackWorkspace lay = stack_workspace_layout(n, l, p);
-    unsigned long long w2[2] = {0, 0};
+    unsigned long long w2[3] = {0, 0, 0};
     uint32_t q[4] = {0, 0, 0, 0};
     hipError_t e = hipMemcpyAsync(w2, (const char *)workspace + lay.work, sizeof w2,
                                   hipMemcpyDeviceToHost, stream);
@@ -327,6 +334,7 @@ l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *wor
     out[0] = w2[0];
     out[1] = w2[1];
     out[2] = q[1];
+    out[3] = w2[2];
     return L1LS_OK;
 }
 
@@ -336,12 +344,17 @@ void l1ls_timing_enable(int32_t on)
     g_timing = on != 0;
 }
 
-int32_t l1ls_timing_read(double *total_ms, int32_t *launches)
+int32_t l1ls_timing_read_kernel(int32_t kernel_class, double *total_ms, int32_t *launches)
 {
+    if (kernel_class < 0 || kernel_class > 2) {
+        if (total_ms) *total_ms = 0.0;
+        if (launches) *launches = 0;
+        return -1;
+    }
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     {
         std::lock_guard<std::mutex> g(g_tmu);
-        ev.swap(g_events);
+        ev.swap(g_events[kernel_class]);
     }
     double tot = 0.0;
     int cnt = 0;
@@ -358,6 +371,11 @@ int32_t l1ls_timing_read(double *total_ms, int32_t *launches)
     if (total_ms) *total_ms = tot;
     if (launches) *launches = cnt;
     return cnt;
+}
+
+int32_t l1ls_timing_read(double *total_ms, int32_t *launches)
+{
+    return l1ls_timing_read_kernel(L1LS_KERNEL_ITERATION, total_ms, launches);
 }
 
 static l1ls_status check_unrolled(int32_t n, int32_t l, int64_t p, int32_t K, int32_t ckpt)

@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, con
     __shared__ double ctl[4];
     const int tid = threadIdx.x, bd = blockDim.x;
     if (tid < 4) queue[tid] = 0u;
-    if (tid < 2) work[tid] = 0ull;
+    if (tid < 4) work[tid] = 0ull;
     const int rows = rows_pad_for_dev(n);
     for (int idx = tid; idx < rows * l_pad; idx += bd) {
         const int r = idx / l_pad, c = idx % l_pad;

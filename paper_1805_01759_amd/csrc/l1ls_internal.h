@@ -40,7 +40,7 @@ struct FistaArgs {
     const StackConsts *consts;
     uint32_t *queue;          // [0] next pixel
     uint32_t *polish_count;   // number of pixels appended to polish_list
-    unsigned long long *work; // [0] pixel forward products, [1] pixel adjoint products
+    unsigned long long *work; // [0] pixel forward products, [1] pixel adjoint products, [2] refinement flops
     int32_t *polish_list;
     int32_t fista_cap;        // retire unsolved pixels after this many iterations
     float tol, c_alpha;
@@ -79,6 +79,7 @@ struct PolishArgsDev {
     const uint32_t *count;    // number of listed pixels
     const int32_t *list;      // pixel indices
     uint32_t *status;         // workspace status: POLISHED is or-ed in
+    unsigned long long *work; // [2] accumulates the refinement's FP64 flops
     int32_t rounds;
     int32_t mode;             // 1: refine pixels whose FP64 KKT > tol; 2: refine all
     float tol;

@@ -432,6 +432,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
     const double gstop = a.mode == 2 ? 1e-13 : 1e-3 * (double)a.tol;
     const double kstop = a.mode == 2 ? 1e-10 : 1e-2 * (double)a.tol;
     const uint32_t count = *a.count;
+    // FP64 flops of the algorithm (wave-uniform): 8 per complex multiply-add
+    unsigned long long fl = 0;
+    const unsigned long long f8n = 8ull * (unsigned long long)a.n;
     for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
         const int64_t p = a.list[item];
         const float lam_f = a.lambda[p * a.lambda_stride];
@@ -448,6 +451,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         __syncthreads();
         // objective and FP64 natural KKT residual of the starting point
         residual_start(a, sh, b);
+        fl += f8n * (unsigned long long)(sh.cnt + a.l);
         double fbest, kk0;
         int vdummy;
         full_pass<true>(a, sh, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
@@ -511,6 +515,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             for (int it = 0; it < 50 && s > 0; ++it) {
                 const int m2 = 2 * s;
                 const double ph = phi_support(a, sh, b0, b1, sh.z, s, lam);
+                fl += 2ull * f8n * (unsigned long long)s;  // residual and gradient
                 // gradient of phi on the working set (real pairs); 4 lane groups
                 // over the rows of A_S
                 double gmax = 0.0;
@@ -549,6 +554,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                 bool ok = false;
                 for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
                     build_hessian(a, sh, s, lam, mu);
+                    fl += f8n * (unsigned long long)(s * (s + 1) / 2) +
+                          (unsigned long long)(m2 * m2 * m2 / 3 + 2 * m2 * m2);
                     if (m2 <= 8) {
                         ok = newton_regs<8>(sh, m2, dv);
                     } else {
@@ -610,6 +617,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                         sh.zt[t] = make_double2(sh.z[t].x + step * sh.dir[t], sh.z[t].y + step * sh.dir[t + s]);
                     __syncthreads();
                     const double pn = phi_support(a, sh, b0, b1, sh.zt, s, lam);
+                    fl += f8n * (unsigned long long)s;
                     if (pn <= ph + 1e-4 * step * slope) { acc = true; break; }
                     step *= 0.5;
                 }
@@ -624,6 +632,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             double F, kk;
             int vidx;
             full_pass<false>(a, sh, s, 0, lam, lf, inv_lf, F, kk, vidx);
+            fl += f8n * (unsigned long long)(s + a.l);
             if (F <= fbest) {
                 fbest = F;
                 for (int m = lane; m < a.l_pad; m += 64) {
@@ -650,6 +659,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             gr = wsum(gr);
             gi = wsum(gi);
             cn = wsum(cn);
+            fl += f8n;
             // argmin_z |a z + r|^2 + lambda |z| = -S_{lambda/2}(a^H r) / ||a||^2
             const double mag = sqrt(gr * gr + gi * gi), tau = 0.5 * lam;
             const double sc = mag > tau ? (1.0 - tau / mag) / cn : 0.0;
@@ -665,6 +675,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         if (lane == 0) a.status[p] |= L1LS_PX_POLISHED;
         __syncthreads();
     }
+    if (lane == 0 && fl) atomicAdd(&a.work[2], fl);
 }
 
 size_t polish_lds_bytes(int n, int l_pad)
