@@ -182,54 +182,73 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, int s, int n
     }
     const double tau = lam * inv_lf, tau2 = tau * tau;
     const double lv = lam * (1.0 + 1e-12), lv2 = lv * lv;
-    for (int m = lane; m < a.l; m += 64) {
-        double xr, xi;
-        if (START) {
-            const float2 v = sh.best[m];
-            xr = v.x;
-            xi = v.y;
-        } else {
-            const int t = sh.sidx[m];
-            const double2 v = t >= 0 ? sh.z[t] : make_double2(0.0, 0.0);
-            xr = v.x;
-            xi = v.y;
+    // Lane bins m = lane + 64 c, two at a time: each batch of eight rows loads the
+    // two columns together (16 loads in flight) and reuses each r_n across them.
+    const int nb = (a.l + 63) / 64;
+    for (int c0 = 0; c0 < nb; c0 += 2) {
+        int mk[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int m = lane + 64 * (c0 + k);
+            mk[k] = m < a.l ? m : 0;  // a column in range; its result is discarded
         }
-        // g_m = 2 a_m^H r, the column read eight rows at a time (loads in flight together)
-        double gr = 0.0, gi = 0.0;
-        const float2 *col = a.A + m;
+        double gr[2] = {}, gi[2] = {};
         int nn = 0;
         for (; nn + 8 <= a.n; nn += 8) {
-            float2 af[8];
+            float2 af[2][8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) af[u] = col[(size_t)(nn + u) * a.l_pad];
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) af[k][u] = a.A[(unsigned)((nn + u) * a.l_pad + mk[k])];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const double2 rv = sh.r[nn + u];
-                gr += af[u].x * rv.x + af[u].y * rv.y;
-                gi += af[u].x * rv.y - af[u].y * rv.x;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    gr[k] += af[k][u].x * rv.x + af[k][u].y * rv.y;
+                    gi[k] += af[k][u].x * rv.y - af[k][u].y * rv.x;
+                }
             }
         }
         for (; nn < a.n; ++nn) {
-            const float2 af = col[(size_t)nn * a.l_pad];
             const double2 rv = sh.r[nn];
-            gr += af.x * rv.x + af.y * rv.y;
-            gi += af.x * rv.y - af.y * rv.x;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const float2 af = a.A[(unsigned)(nn * a.l_pad + mk[k])];
+                gr[k] += af.x * rv.x + af.y * rv.y;
+                gi[k] += af.x * rv.y - af.y * rv.x;
+            }
         }
-        gr *= 2.0;
-        gi *= 2.0;
-        const double vr = xr - gr * inv_lf, vi = xi - gi * inv_lf;
-        const double m2 = vr * vr + vi * vi;
-        double er = xr, ei = xi;  // x - prox(v), prox(v) = 0 when |v| <= tau
-        if (m2 > tau2) {
-            const double sc = 1.0 - tau / sqrt(m2);
-            er = xr - vr * sc;
-            ei = xi - vi * sc;
-        }
-        km = fmax(km, er * er + ei * ei);
-        const double gm2 = gr * gr + gi * gi;
-        if (xr == 0.0 && xi == 0.0 && gm2 > lv2 && gm2 > vbest) {
-            vbest = gm2;
-            vidx = m;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int m = lane + 64 * (c0 + k);
+            if (m >= a.l) continue;
+            double xr, xi;
+            if (START) {
+                const float2 v = sh.best[m];
+                xr = v.x;
+                xi = v.y;
+            } else {
+                const int t = sh.sidx[m];
+                const double2 v = t >= 0 ? sh.z[t] : make_double2(0.0, 0.0);
+                xr = v.x;
+                xi = v.y;
+            }
+            const double g_r = 2.0 * gr[k], g_i = 2.0 * gi[k];  // g_m = 2 a_m^H r
+            const double vr = xr - g_r * inv_lf, vi = xi - g_i * inv_lf;
+            const double m2 = vr * vr + vi * vi;
+            double er = xr, ei = xi;  // x - prox(v), prox(v) = 0 when |v| <= tau
+            if (m2 > tau2) {
+                const double sc = 1.0 - tau / sqrt(m2);
+                er = xr - vr * sc;
+                ei = xi - vi * sc;
+            }
+            km = fmax(km, er * er + ei * ei);
+            const double gm2 = g_r * g_r + g_i * g_i;
+            if (xr == 0.0 && xi == 0.0 && gm2 > lv2 && gm2 > vbest) {
+                vbest = gm2;
+                vidx = m;
+            }
         }
     }
     F = wsum(acc + lam * l1);
@@ -558,6 +577,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                           (unsigned long long)(m2 * m2 * m2 / 3 + 2 * m2 * m2);
                     if (m2 <= 8) {
                         ok = newton_regs<8>(sh, m2, dv);
+                    } else if (m2 <= 10) {
+                        ok = newton_regs<10>(sh, m2, dv);
                     } else {
                         ok = cholesky(sh, m2);
                         if (ok) dv = newton_dir(sh, m2);
