@@ -6,8 +6,9 @@ namespace l1ls {
 
 template <int NZB, int KB, bool ALDS, int PREC>
 hipError_t launch_one(const FistaArgs &a, int max_groups, hipStream_t s);
-template <int T, int KB, bool ALDS>
+template <int T, int KB, bool ALDS, int PREC>
 hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s);
+size_t fm_bf_planes_bytes_host(int rows, int l_pad);
 
 __device__ __forceinline__ int rows_pad_for_dev(int n) { return 16 * ((n + 15) / 16); }
 
@@ -178,32 +179,55 @@ static hipError_t launch_prec(const FistaArgs &a, int max_groups, hipStream_t s)
 }
 
 // FP32 contractions: the kernel with split real/imaginary accumulators
-size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds)
+size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precision)
 {
     const int rows = rows_pad_for(n), T = rows / 16;
-    size_t off = a_lds ? (((size_t)rows * (l_pad + 2) * sizeof(float2) + 15) & ~(size_t)15) : 0;
+    size_t off = 0;
+    if (precision == L1LS_SPLIT_BF16)
+        off = (fm_bf_planes_bytes_host(rows, l_pad) + 15) & ~(size_t)15;
+    else if (a_lds)
+        off = ((size_t)rows * (l_pad + 2) * sizeof(float2) + 15) & ~(size_t)15;
     off += (size_t)waves * 2 * T * 64 * 16;
     off += (size_t)waves * 16 * 16;
     off += 16;
     return off;
 }
 
+// one wave per SIMD: a workgroup of W waves may use W/4 of the CU's 160 KB
+static bool mfma_lds_fits(const FistaArgs &a, int precision)
+{
+    return fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, true, precision) <= (size_t)160 * 1024 * a.waves / 4;
+}
+
 template <int T>
 static hipError_t launch_mfma_t(const FistaArgs &a, int max_groups, hipStream_t s)
 {
-    // one wave per SIMD: a workgroup of W waves may use W/4 of the CU's 160 KB
-    const bool lds = fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, true) <= (size_t)160 * 1024 * a.waves / 4;
+    const bool lds = mfma_lds_fits(a, L1LS_FP32);
     if (slice_blocks_for(a.l) == 8)
-        return lds ? launch_mfma_one<T, 4, true>(a, max_groups, s)
-                   : launch_mfma_one<T, 4, false>(a, max_groups, s);
-    return lds ? launch_mfma_one<T, 8, true>(a, max_groups, s)
-               : launch_mfma_one<T, 8, false>(a, max_groups, s);
+        return lds ? launch_mfma_one<T, 4, true, L1LS_FP32>(a, max_groups, s)
+                   : launch_mfma_one<T, 4, false, L1LS_FP32>(a, max_groups, s);
+    return lds ? launch_mfma_one<T, 8, true, L1LS_FP32>(a, max_groups, s)
+               : launch_mfma_one<T, 8, false, L1LS_FP32>(a, max_groups, s);
 }
 
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s)
 {
-    if (precision == L1LS_SPLIT_BF16) return launch_prec<L1LS_SPLIT_BF16>(a, max_groups, s);
-    switch (rows_pad_for(a.n) / 16) {
+    const int T = rows_pad_for(a.n) / 16;
+    if (precision == L1LS_SPLIT_BF16) {
+        // split re/im layout with bf16 planes in LDS where they fit (64 unknowns per
+        // wave); otherwise the real-embedded kernel
+        if (slice_blocks_for(a.l) == 8 && mfma_lds_fits(a, L1LS_SPLIT_BF16)) {
+            switch (T) {
+            case 1: return launch_mfma_one<1, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
+            case 2: return launch_mfma_one<2, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
+            case 3: return launch_mfma_one<3, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
+            case 4: return launch_mfma_one<4, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
+            default: break;
+            }
+        }
+        return launch_prec<L1LS_SPLIT_BF16>(a, max_groups, s);
+    }
+    switch (T) {
     case 1: return launch_mfma_t<1>(a, max_groups, s);
     case 2: return launch_mfma_t<2>(a, max_groups, s);
     case 3: return launch_mfma_t<3>(a, max_groups, s);

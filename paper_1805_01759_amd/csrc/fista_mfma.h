@@ -35,6 +35,15 @@
 //   ||r-bar||^2 - ||r_k||^2 = <r-bar - r_k, r-bar + r_k>,
 //   ||x-bar||_1 - ||x^k||_1 = sum_m (|x-bar_m| - |x^k_m|)   (|x^k_m| kept per unknown).
 //
+// Split-BF16 (PREC = L1LS_SPLIT_BF16): every real product a.b is formed as
+// hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b) with x = hi(x) + lo(x), hi = RNE bf16 of x,
+// lo = RNE bf16 of the remainder, accumulated in FP32 by v_mfma_f32_16x16x16bf16_1k,
+// whose four k values per lane are the q = 0..3 of the FP32 form.  A is split
+// once into four bf16 planes (re/im x hi/lo) staged in LDS twice: row-major for
+// the forward product (four consecutive m per lane read) and transposed for the
+// adjoint (four consecutive n per lane read), so the A operands are plain 8-byte
+// LDS loads; d and r are split per product with the hardware bf16 conversion.
+//
 // Pixels retire when the FP32 KKT residual passes tol, or after fista_cap
 // iterations; a retired slot is refilled at once from a global atomic queue.
 #pragma once
@@ -50,6 +59,35 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f4 mfma_bf(s4 a, s4 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// v = hi + lo with hi = RNE bf16(v), lo = RNE bf16(v - hi), four at a time
+__device__ __forceinline__ void split4(float v0, float v1, float v2, float v3, s4 &hi, s4 &lo)
+{
+    const bf2 h01 = {(__bf16)v0, (__bf16)v1}, h23 = {(__bf16)v2, (__bf16)v3};
+    const bf2 l01 = {(__bf16)(v0 - (float)h01[0]), (__bf16)(v1 - (float)h01[1])};
+    const bf2 l23 = {(__bf16)(v2 - (float)h23[0]), (__bf16)(v3 - (float)h23[1])};
+    const uint2 hu = make_uint2(__builtin_bit_cast(uint32_t, h01), __builtin_bit_cast(uint32_t, h23));
+    const uint2 lu = make_uint2(__builtin_bit_cast(uint32_t, l01), __builtin_bit_cast(uint32_t, l23));
+    hi = __builtin_bit_cast(s4, hu);
+    lo = __builtin_bit_cast(s4, lu);
+}
+// -x for four packed bf16 values (sign bits)
+__device__ __forceinline__ s4 neg4(s4 v)
+{
+    uint2 u = __builtin_bit_cast(uint2, v);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    return __builtin_bit_cast(s4, u);
+}
+__device__ __forceinline__ s4 lds4(const uint16_t *p) { return *reinterpret_cast<const s4 *>(p); }
 
 // Sum / max over the four lanes (h = 0..3) that hold one pixel slot.
 __device__ __forceinline__ float sum_h(float v)
@@ -102,12 +140,21 @@ struct AView {
 }  // namespace fm
 
 // LDS row stride of the staged A (float2 units): l_pad + 2 spreads the rows of
-// one load over distinct banks.
+// one load over distinct banks.  Split-BF16 planes: row-major stride l_pad + 4,
+// transposed stride 16 T + 4 (bf16 units).
 __host__ __device__ inline int fm_lds_ld(int l_pad) { return l_pad + 2; }
+__host__ __device__ inline int fm_bf_ldf(int l_pad) { return l_pad + 4; }
+__host__ __device__ inline int fm_bf_lda(int rows) { return rows + 4; }
+__host__ __device__ inline size_t fm_bf_planes_bytes(int rows, int l_pad)
+{
+    return ((size_t)4 * rows * fm_bf_ldf(l_pad) + (size_t)4 * l_pad * fm_bf_lda(rows)) * sizeof(uint16_t);
+}
 
-template <int T, int KB, bool ALDS>
+template <int T, int KB, bool ALDS, int PREC>
 __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
 {
+    static_assert(PREC == L1LS_FP32 || ALDS, "split-BF16 stages its A planes in LDS");
+    constexpr bool BF = PREC == L1LS_SPLIT_BF16;
     using fm::f4;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
@@ -122,7 +169,11 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
 
     size_t off = 0;
     float2 *sA = reinterpret_cast<float2 *>(smem);
-    if (ALDS) off = ((size_t)rows * fm_lds_ld(a.l_pad) * sizeof(float2) + 15) & ~(size_t)15;
+    uint16_t *sF = reinterpret_cast<uint16_t *>(smem);  // split-BF16 planes [4][rows][ldf]
+    const int ldf = fm_bf_ldf(a.l_pad), lda = fm_bf_lda(rows);
+    uint16_t *sT = sF + (size_t)4 * rows * ldf;          // transposed planes [4][l_pad][lda]
+    if (BF) off = (fm_bf_planes_bytes(rows, a.l_pad) + 15) & ~(size_t)15;
+    else if (ALDS) off = ((size_t)rows * fm_lds_ld(a.l_pad) * sizeof(float2) + 15) & ~(size_t)15;
     f4 *sPW = reinterpret_cast<f4 *>(smem + off);   // [W][2T][64] forward partials
     off += (size_t)W * 2 * T * 64 * sizeof(f4);
     f4 *sPS = reinterpret_cast<f4 *>(smem + off);   // [W][16] per-slot partial scalars
@@ -130,7 +181,23 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
     uint32_t *sQ = reinterpret_cast<uint32_t *>(smem + off);
 
     fm::AView Av;
-    if (ALDS) {
+    if constexpr (BF) {
+        // planes c = 0 re hi, 1 im hi, 2 re lo, 3 im lo
+        for (int idx = tid; idx < rows * a.l_pad; idx += blockDim.x) {
+            const int row = idx / a.l_pad, m = idx % a.l_pad;
+            const float2 v = a.A[(size_t)row * a.l_pad + m];
+            const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+            const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
+            const uint16_t pv[4] = {__builtin_bit_cast(uint16_t, rh), __builtin_bit_cast(uint16_t, ih),
+                                    __builtin_bit_cast(uint16_t, rl), __builtin_bit_cast(uint16_t, il)};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                sF[((size_t)c * rows + row) * ldf + m] = pv[c];
+                sT[((size_t)c * a.l_pad + m) * lda + row] = pv[c];
+            }
+        }
+        __syncthreads();
+    } else if (ALDS) {
         const int ld = fm_lds_ld(a.l_pad), half = a.l_pad / 2;
         for (int idx = tid; idx < rows * half; idx += blockDim.x) {
             const int row = idx / half, c2 = idx % half;
@@ -222,6 +289,47 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
 
     // ---- G = 2 A^H r for the wave's unknowns (all slots)
     auto adjoint = [&]() {
+        if constexpr (BF) {
+            fm::s4 rrh[T], rrl[T], rih[T], ril[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                fm::split4(2.0f * Rr[t][0], 2.0f * Rr[t][1], 2.0f * Rr[t][2], 2.0f * Rr[t][3], rrh[t], rrl[t]);
+                fm::split4(2.0f * Ri[t][0], 2.0f * Ri[t][1], 2.0f * Ri[t][2], 2.0f * Ri[t][3], rih[t], ril[t]);
+            }
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                f4 gr = f4{0.0f, 0.0f, 0.0f, 0.0f}, gi = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                const int m = m_base + 16 * b + j;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const int n0 = 16 * t + 4 * h;
+                    const fm::s4 arh = fm::lds4(sT + ((size_t)0 * a.l_pad + m) * lda + n0);
+                    const fm::s4 aih = fm::lds4(sT + ((size_t)1 * a.l_pad + m) * lda + n0);
+                    const fm::s4 arl = fm::lds4(sT + ((size_t)2 * a.l_pad + m) * lda + n0);
+                    const fm::s4 ail = fm::lds4(sT + ((size_t)3 * a.l_pad + m) * lda + n0);
+                    // G_re += A_re (2 r_re) + A_im (2 r_im);  G_im += A_re (2 r_im) - A_im (2 r_re)
+                    gr = fm::mfma_bf(arh, rrh[t], gr);
+                    gr = fm::mfma_bf(arh, rrl[t], gr);
+                    gr = fm::mfma_bf(arl, rrh[t], gr);
+                    gr = fm::mfma_bf(aih, rih[t], gr);
+                    gr = fm::mfma_bf(aih, ril[t], gr);
+                    gr = fm::mfma_bf(ail, rih[t], gr);
+                    gi = fm::mfma_bf(arh, rih[t], gi);
+                    gi = fm::mfma_bf(arh, ril[t], gi);
+                    gi = fm::mfma_bf(arl, rih[t], gi);
+                    gi = fm::mfma_bf(aih, fm::neg4(rrh[t]), gi);
+                    gi = fm::mfma_bf(aih, fm::neg4(rrl[t]), gi);
+                    gi = fm::mfma_bf(ail, fm::neg4(rrh[t]), gi);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    Gr[b][q] = gr[q];
+                    Gi[b][q] = gi[q];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            return;
+        }
         float r2r[T][4], r2i[T][4], nr2r[T][4];
 #pragma unroll
         for (int t = 0; t < T; ++t)
@@ -303,6 +411,35 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
                     s1 += axb - AX[b][q];
                 }
                 const int m0 = m_base + 16 * b + 4 * h;
+                if constexpr (BF) {
+                    fm::s4 drh, drl, dih, dil;
+                    fm::split4(dr[0], dr[1], dr[2], dr[3], drh, drl);
+                    fm::split4(di[0], di[1], di[2], di[3], dih, dil);
+                    const fm::s4 ndih = fm::neg4(dih), ndil = fm::neg4(dil);
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        const int row = 16 * t + j;
+                        const fm::s4 arh = fm::lds4(sF + ((size_t)0 * rows + row) * ldf + m0);
+                        const fm::s4 aih = fm::lds4(sF + ((size_t)1 * rows + row) * ldf + m0);
+                        const fm::s4 arl = fm::lds4(sF + ((size_t)2 * rows + row) * ldf + m0);
+                        const fm::s4 ail = fm::lds4(sF + ((size_t)3 * rows + row) * ldf + m0);
+                        // W_re += A_re d_re + A_im (-d_im);  W_im += A_im d_re + A_re d_im
+                        Wr[t] = fm::mfma_bf(arh, drh, Wr[t]);
+                        Wr[t] = fm::mfma_bf(arh, drl, Wr[t]);
+                        Wr[t] = fm::mfma_bf(arl, drh, Wr[t]);
+                        Wr[t] = fm::mfma_bf(aih, ndih, Wr[t]);
+                        Wr[t] = fm::mfma_bf(aih, ndil, Wr[t]);
+                        Wr[t] = fm::mfma_bf(ail, ndih, Wr[t]);
+                        Wi[t] = fm::mfma_bf(aih, drh, Wi[t]);
+                        Wi[t] = fm::mfma_bf(aih, drl, Wi[t]);
+                        Wi[t] = fm::mfma_bf(ail, drh, Wi[t]);
+                        Wi[t] = fm::mfma_bf(arh, dih, Wi[t]);
+                        Wi[t] = fm::mfma_bf(arh, dil, Wi[t]);
+                        Wi[t] = fm::mfma_bf(arl, dih, Wi[t]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    continue;
+                }
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
                     const f4 a01 = Av.load4(16 * t + j, m0);      // (re, im) of m0, m0 + 1
@@ -493,11 +630,11 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
 
 
 
-template <int T, int KB, bool ALDS>
+template <int T, int KB, bool ALDS, int PREC>
 hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s)
 {
-    const size_t lds = fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, ALDS);
-    auto kern = fista_mfma_kernel<T, KB, ALDS>;
+    const size_t lds = fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, ALDS, PREC);
+    auto kern = fista_mfma_kernel<T, KB, ALDS, PREC>;
     static bool attr_done = false;  // per instantiation
     if (!attr_done) {
         hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -124,7 +124,7 @@ hipError_t launch_unrolled_backward(int n, int l, int64_t p, const float2 *B, fl
                                     const float2 *dX, float2 *dB, float *dlambda, float *dxi,
                                     void *ws, hipStream_t st);
 size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds);
-size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds);
+size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precision);
 bool fista_a_fits_lds(int n, int l_pad, int waves, int zb);
 
 }  // namespace l1ls
