@@ -3,7 +3,7 @@
 // minimiser to FP64 accuracy and catches pixels the FP32 iteration left.
 //
 // Per pixel (one 64-lane workgroup), starting from the working set S of the
-// local maxima of |x| of the FP32 iterate, repeat
+// local maxima of |x| of the FP32 iterate and the larger neighbour of each, repeat
 //   * damped Newton on phi(z) = ||A_S z - b||^2 + lambda sum |z_s| over the
 //     working set (|S| <= kMaxSupp), with the real Hessian
 //       2 [[Re G, -Im G], [Im G, Re G]] + lambda blkdiag((I - u u^T)/|z_s|),
@@ -524,6 +524,32 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             }
             __syncthreads();
         }
+        // ... and the larger neighbour of each peak (the exact solution of an
+        // off-grid scatterer usually sits on two adjacent bins; seeding both saves
+        // the round that would admit the second as a violator)
+        if (lane == 0) {
+            const int np = sh.cnt;
+            int cnt = np;
+            for (int t = 0; t < np && cnt < kMaxSupp; ++t) {
+                const int m = sh.S[t];
+                const float2 xl = m > 0 ? sh.best[m - 1] : make_float2(0.0f, 0.0f);
+                const float2 xr = m + 1 < a.l ? sh.best[m + 1] : make_float2(0.0f, 0.0f);
+                const double ml = (double)xl.x * xl.x + (double)xl.y * xl.y;
+                const double mr = (double)xr.x * xr.x + (double)xr.y * xr.y;
+                const int nb = ml >= mr ? m - 1 : m + 1;
+                const double mn = ml >= mr ? ml : mr;
+                if (!(mn > 0.0)) continue;
+                bool dup = false;
+                for (int u = 0; u < cnt; ++u) dup = dup || sh.S[u] == nb;
+                if (dup) continue;
+                const float2 xf = sh.best[nb];
+                sh.S[cnt] = nb;
+                sh.z[cnt] = make_double2(xf.x, xf.y);
+                ++cnt;
+            }
+            sh.cnt = cnt;
+        }
+        __syncthreads();
         int s = sh.cnt;
         for (int e = lane; e < a.n * s; e += 64) {  // all columns of the working set at once
             const int nn = e / s, t = e % s;
