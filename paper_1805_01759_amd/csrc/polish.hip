@@ -601,7 +601,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                     build_hessian(a, sh, s, lam, mu);
                     fl += f8n * (unsigned long long)(s * (s + 1) / 2) +
                           (unsigned long long)(m2 * m2 * m2 / 3 + 2 * m2 * m2);
-                    if (m2 <= 8) {
+                    if (m2 <= 4) {
+                        ok = newton_regs<4>(sh, m2, dv);
+                    } else if (m2 <= 6) {
+                        ok = newton_regs<6>(sh, m2, dv);
+                    } else if (m2 <= 8) {
                         ok = newton_regs<8>(sh, m2, dv);
                     } else if (m2 <= 10) {
                         ok = newton_regs<10>(sh, m2, dv);
