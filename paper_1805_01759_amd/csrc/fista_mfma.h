@@ -396,25 +396,74 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
 #pragma unroll
             for (int t = 0; t < T; ++t) Wr[t] = Wi[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
             float d2 = 0.0f, s1 = 0.0f;
-#pragma unroll
-            for (int b = 0; b < KB; ++b) {
-                float dr[4], di[4], ndi[4];
+            // element work of block b: extrapolate, gradient step, prox, d = x-bar - y
+            float dr[KB][4], di[KB][4];
+            auto element_block = [&](int b) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     float y_r, y_i, xb_r, xb_i, axb;
                     fm::trial_one(Xr[b][q], Xi[b][q], Xpr[b][q], Xpi[b][q], Gr[b][q], Gi[b][q],
                                   Gpr[b][q], Gpi[b][q], beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
-                    dr[q] = xb_r - y_r;
-                    di[q] = xb_i - y_i;
-                    ndi[q] = -di[q];
-                    d2 = fmaf(dr[q], dr[q], fmaf(di[q], di[q], d2));
+                    dr[b][q] = xb_r - y_r;
+                    di[b][q] = xb_i - y_i;
+                    d2 = fmaf(dr[b][q], dr[b][q], fmaf(di[b][q], di[b][q], d2));
                     s1 += axb - AX[b][q];
                 }
-                const int m0 = m_base + 16 * b + 4 * h;
-                if constexpr (BF) {
+            };
+            if constexpr (!BF) {
+                // software pipeline: block b + 1's element work is interleaved with
+                // block b's MFMAs (one wave per SIMD: the VALU work hides under the
+                // matrix-core passes instead of following them)
+                element_block(0);
+#pragma unroll
+                for (int b = 0; b < KB; ++b) {
+                    const int m0 = m_base + 16 * b + 4 * h;
+                    f4 a01[T], a23[T];
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        a01[t] = Av.load4(16 * t + j, m0);      // (re, im) of m0, m0 + 1
+                        a23[t] = Av.load4(16 * t + j, m0 + 2);  // (re, im) of m0 + 2, m0 + 3
+                    }
+                    if (b + 1 < KB) element_block(b + 1);
+                    float ndi[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ndi[q] = -di[b][q];
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        Wr[t] = fm::mfma(a01[t][0], dr[b][0], Wr[t]);
+                        Wr[t] = fm::mfma(a01[t][1], ndi[0], Wr[t]);
+                        Wi[t] = fm::mfma(a01[t][1], dr[b][0], Wi[t]);
+                        Wi[t] = fm::mfma(a01[t][0], di[b][0], Wi[t]);
+                        Wr[t] = fm::mfma(a01[t][2], dr[b][1], Wr[t]);
+                        Wr[t] = fm::mfma(a01[t][3], ndi[1], Wr[t]);
+                        Wi[t] = fm::mfma(a01[t][3], dr[b][1], Wi[t]);
+                        Wi[t] = fm::mfma(a01[t][2], di[b][1], Wi[t]);
+                        Wr[t] = fm::mfma(a23[t][0], dr[b][2], Wr[t]);
+                        Wr[t] = fm::mfma(a23[t][1], ndi[2], Wr[t]);
+                        Wi[t] = fm::mfma(a23[t][1], dr[b][2], Wi[t]);
+                        Wi[t] = fm::mfma(a23[t][0], di[b][2], Wi[t]);
+                        Wr[t] = fm::mfma(a23[t][2], dr[b][3], Wr[t]);
+                        Wr[t] = fm::mfma(a23[t][3], ndi[3], Wr[t]);
+                        Wi[t] = fm::mfma(a23[t][3], dr[b][3], Wi[t]);
+                        Wi[t] = fm::mfma(a23[t][2], di[b][3], Wi[t]);
+                    }
+                    if (b + 1 < KB) {
+                        // 16 T MFMAs with the next block's element work between them
+#pragma unroll
+                        for (int u = 0; u < 16 * T; ++u) {
+                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // then up to 6 VALU
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < KB; ++b) {
+                    element_block(b);
+                    const int m0 = m_base + 16 * b + 4 * h;
                     fm::s4 drh, drl, dih, dil;
-                    fm::split4(dr[0], dr[1], dr[2], dr[3], drh, drl);
-                    fm::split4(di[0], di[1], di[2], di[3], dih, dil);
+                    fm::split4(dr[b][0], dr[b][1], dr[b][2], dr[b][3], drh, drl);
+                    fm::split4(di[b][0], di[b][1], di[b][2], di[b][3], dih, dil);
                     const fm::s4 ndih = fm::neg4(dih), ndil = fm::neg4(dil);
 #pragma unroll
                     for (int t = 0; t < T; ++t) {
@@ -438,28 +487,6 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
                         Wi[t] = fm::mfma_bf(arl, dih, Wi[t]);
                     }
                     __builtin_amdgcn_sched_barrier(0);
-                    continue;
-                }
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    const f4 a01 = Av.load4(16 * t + j, m0);      // (re, im) of m0, m0 + 1
-                    const f4 a23 = Av.load4(16 * t + j, m0 + 2);  // (re, im) of m0 + 2, m0 + 3
-                    Wr[t] = fm::mfma(a01[0], dr[0], Wr[t]);
-                    Wr[t] = fm::mfma(a01[1], ndi[0], Wr[t]);
-                    Wi[t] = fm::mfma(a01[1], dr[0], Wi[t]);
-                    Wi[t] = fm::mfma(a01[0], di[0], Wi[t]);
-                    Wr[t] = fm::mfma(a01[2], dr[1], Wr[t]);
-                    Wr[t] = fm::mfma(a01[3], ndi[1], Wr[t]);
-                    Wi[t] = fm::mfma(a01[3], dr[1], Wi[t]);
-                    Wi[t] = fm::mfma(a01[2], di[1], Wi[t]);
-                    Wr[t] = fm::mfma(a23[0], dr[2], Wr[t]);
-                    Wr[t] = fm::mfma(a23[1], ndi[2], Wr[t]);
-                    Wi[t] = fm::mfma(a23[1], dr[2], Wi[t]);
-                    Wi[t] = fm::mfma(a23[0], di[2], Wi[t]);
-                    Wr[t] = fm::mfma(a23[2], dr[3], Wr[t]);
-                    Wr[t] = fm::mfma(a23[3], ndi[3], Wr[t]);
-                    Wi[t] = fm::mfma(a23[3], dr[3], Wi[t]);
-                    Wi[t] = fm::mfma(a23[2], di[3], Wi[t]);
                 }
             }
             // cross-wave reduction of the forward partial products and scalars
