@@ -32,7 +32,7 @@ struct UnrolledArgs {
     const float2 *B;
     float lambda, alpha;
     float2 *X;           // p x l output (forward)
-    float2 *tape;        // forward: checkpoints p x (K/ckpt - 1) x 2 x l
+    float2 *tape;        // forward: checkpoints p x (K/ckpt - 1) x (2 l + 2 n); (x, xp) used here
     const float2 *dX;    // backward
     float2 *dB;
     float *part;         // backward: per pixel [lambda-bar, xi-bar_0..n-1]
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(64 * kUWaves) unrolled_forward_kernel(const Un
             unrolled_step(a, s, b, k);
             // checkpoint: state before iteration k + 1, at k = c, 2c, ...
             if (k % a.ckpt == 0 && k / a.ckpt < nck) {
-                float2 *t = a.tape + ((size_t)p * (nck - 1) + (k / a.ckpt - 1)) * 2 * a.l;
+                float2 *t = a.tape + ((size_t)p * (nck - 1) + (k / a.ckpt - 1)) * (2 * a.l + 2 * a.n);
                 for (int j = lane; j < a.l; j += 64) {
                     t[j] = s.x[j];
                     t[a.l + j] = s.xp[j];
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(64 * kUWaves) unrolled_backward_kernel(const U
             if (sg == 0) {
                 for (int j = lane; j < a.l; j += 64) s.x[j] = s.xp[j] = make_float2(0.0f, 0.0f);
             } else {
-                const float2 *t = a.tape + ((size_t)p * (nck - 1) + (sg - 1)) * 2 * a.l;
+                const float2 *t = a.tape + ((size_t)p * (nck - 1) + (sg - 1)) * (2 * a.l + 2 * a.n);
                 for (int j = lane; j < a.l; j += 64) {
                     s.x[j] = t[j];
                     s.xp[j] = t[a.l + j];
@@ -318,6 +318,13 @@ __global__ void __launch_bounds__(256) unrolled_reduce_kernel(const float *part,
 
 // ------------------------------------------------------------------ host side
 
+bool unrolled_tile_supports(int n, int l);
+size_t unrolled_tile_seg_bytes(int n, int l, int ckpt);
+hipError_t launch_unrolled_tile(bool forward, int n, int l, int64_t p, const float2 *A, const float2 *As,
+                                const float2 *B, float lambda, float alpha, int K, int ckpt, float2 *X,
+                                float2 *ck, const float2 *dX, float2 *dB, float *part, void *seg,
+                                int64_t max_groups, hipStream_t st);
+
 static size_t fwd_lds(int n, int l) { return (size_t)kUWaves * (5 * l + 2 * n) * sizeof(float2); }
 static size_t bwd_lds(int n, int l) { return (size_t)kUWaves * (7 * l + 2 * n) * sizeof(float2); }
 
@@ -331,18 +338,29 @@ static int64_t bwd_slots()
 
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
+// checkpoint = (x, xp, r_x, r_xp): the matrix-core kernels restart the residual
+// recursion from it; the wave-per-pixel kernels use the first 2 l entries
 size_t unrolled_tape_bytes(int n, int l, int64_t p, int K, int ckpt)
 {
     const int nck = K / ckpt;
     return al256((size_t)n * l * sizeof(float2)) * 2 +
-           al256((size_t)p * (nck > 1 ? nck - 1 : 0) * 2 * l * sizeof(float2));
+           al256((size_t)p * (nck > 1 ? nck - 1 : 0) * (2 * l + 2 * n) * sizeof(float2));
+}
+
+static int64_t tile_groups()
+{
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus;
 }
 
 size_t unrolled_bwd_ws_bytes(int n, int l, int64_t p, int K, int ckpt)
 {
     (void)K;
-    return al256((size_t)p * (n + 1) * sizeof(float)) +
-           al256((size_t)bwd_slots() * ckpt * (2 * l + n) * sizeof(float2));
+    const size_t wave_seg = (size_t)bwd_slots() * ckpt * (2 * l + n) * sizeof(float2);
+    const size_t tile_seg = unrolled_tile_supports(n, l) ? (size_t)tile_groups() * unrolled_tile_seg_bytes(n, l, ckpt) : 0;
+    return al256((size_t)p * (n + 1) * sizeof(float)) + al256(wave_seg > tile_seg ? wave_seg : tile_seg);
 }
 
 hipError_t launch_unrolled_forward(int n, int l, int64_t p, const float *xi, const float *s,
@@ -357,6 +375,9 @@ hipError_t launch_unrolled_forward(int n, int l, int64_t p, const float *xi, con
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p == 0) return e;
     UnrolledArgs a{};
+    if (unrolled_tile_supports(n, l))
+        return launch_unrolled_tile(true, n, l, p, A, As, B, lambda, alpha, K, ckpt, X, ck, nullptr,
+                                    nullptr, nullptr, nullptr, 0, st);
     a.n = n; a.l = l; a.K = K; a.ckpt = ckpt; a.p = p;
     a.A = A; a.As = As; a.B = B; a.lambda = lambda; a.alpha = alpha; a.X = X; a.tape = ck;
     const size_t lds = fwd_lds(n, l);
@@ -385,7 +406,11 @@ hipError_t launch_unrolled_backward(int n, int l, int64_t p, const float2 *B, fl
     a.part = (float *)w;
     a.seg = (float2 *)(w + al256((size_t)p * (n + 1) * sizeof(float)));
     a.slots = bwd_slots();
-    if (p > 0) {
+    if (p > 0 && unrolled_tile_supports(n, l)) {
+        hipError_t e = launch_unrolled_tile(false, n, l, p, a.A, a.As, B, lambda, alpha, K, ckpt, nullptr,
+                                            a.tape, dX, dB, a.part, a.seg, tile_groups(), st);
+        if (e != hipSuccess) return e;
+    } else if (p > 0) {
         const size_t lds = bwd_lds(n, l);
         hipFuncSetAttribute((const void *)unrolled_backward_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

@@ -84,3 +84,34 @@ def test_checkpoint_spacing_does_not_change_gradients(dev):
         grads.append((Bd.grad.clone(), xid.grad.clone()))
     for g in grads[1:]:
         assert torch.equal(g[0], grads[0][0]) and torch.equal(g[1], grads[0][1])
+
+
+def test_wave_kernels_outside_the_tile_shapes(dev, orc):
+    """N = 40, L = 300 falls outside the matrix-core tile (N <= 32, L <= 256): the
+    wave-per-pixel kernels run; forward and gradients against the FP64 references."""
+    from oracle import unrolled_ref
+    from paper_1805_01759_amd.unrolled import unrolled
+    geom = synth.make_geometry(5, 40, 300, 300.0, -60.0, 60.0, stack=7)
+    rng = np.random.default_rng(1805)
+    p, K = 32, 40
+    B = (rng.standard_normal((p, 40)) + 1j * rng.standard_normal((p, 40))).astype(np.complex64)
+    lam = 4.0
+    xi = torch.tensor(geom.xi, dtype=torch.float32)
+    s = torch.tensor(geom.s, dtype=torch.float32)
+    A64 = np.exp(-2j * np.pi * np.outer(xi.double().numpy(), s.double().numpy()))
+    alpha = 1.0 / (2 * np.linalg.eigvalsh(A64 @ A64.conj().T).max())
+    Bd = torch.from_numpy(B).to(dev).requires_grad_(True)
+    xid = xi.to(dev).requires_grad_(True)
+    X = unrolled(Bd, lam, xid, s.to(dev), alpha, K, 10)
+    Xo = orc.unrolled_batch(A64, B.astype(np.complex128), lam, alpha, K)
+    e = np.linalg.norm(X.detach().cpu().numpy() - Xo, axis=1) / np.maximum(np.linalg.norm(Xo, axis=1), 1e-3)
+    assert e.max() < 1e-4, e.max()
+    Xt = np.zeros((p, 300), np.complex128)
+    (X.abs() ** 2).sum().backward()
+    lref, Xref, dB, dlam, dxi = unrolled_ref.loss_and_grads(
+        xi.double(), s.double(), torch.from_numpy(B.astype(np.complex128)), lam, alpha, K,
+        torch.from_numpy(Xt))
+    eB = np.linalg.norm(Bd.grad.cpu().numpy() - dB.numpy()) / np.linalg.norm(dB.numpy())
+    ex = np.linalg.norm(xid.grad.cpu().double().numpy() - dxi.numpy()) / np.linalg.norm(dxi.numpy())
+    print(f"wave kernels: forward e max {e.max():.1e}, grads dB {eB:.2e} dxi {ex:.2e}")
+    assert eB < 1e-4 and ex < 1e-4, (eB, ex)
