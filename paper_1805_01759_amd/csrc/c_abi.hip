@@ -43,6 +43,8 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     size_t off = 0;
     w.a_packed = off;
     off = align_up(off + (size_t)rows_pad_for(n) * l_pad * sizeof(float2), 256);
+    w.a_trans = off;
+    off = align_up(off + (size_t)l_pad * n * sizeof(float2), 256);
     w.gram = off;
     off = align_up(off + (size_t)n * n * sizeof(double2), 256);
     w.consts = off;
@@ -165,7 +167,8 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     int32_t *plist = (int32_t *)(w + lay.polish_list);
 
     unsigned long long *work = (unsigned long long *)(w + lay.work);
-    hipError_t e = launch_setup(n, l, l_pad, (const float2 *)A, Ap, gram, consts, queue, work, s);
+    float2 *At = (float2 *)(w + lay.a_trans);
+    hipError_t e = launch_setup(n, l, l_pad, (const float2 *)A, Ap, At, gram, consts, queue, work, s);
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "setup launch: %s", hipGetErrorString(e));
 
     FistaArgs fa;
@@ -175,6 +178,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     fa.waves = waves;
     fa.p = p;
     fa.A = Ap;
+    fa.At = At;
     fa.B = (const float2 *)B;
     fa.lambda = lambda;
     fa.lambda_stride = lambda_stride;

@@ -17,7 +17,7 @@ __device__ __forceinline__ int rows_pad_for_dev(int n) { return 16 * ((n + 15) /
 // L_f = 2 lambda_max(A A^H) by FP64 power iteration on the Gram matrix, and
 // reset the work queue.  One workgroup of 256 threads.
 __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, const float2 *A,
-                                                    float2 *Ap, double2 *M, StackConsts *consts,
+                                                    float2 *Ap, float2 *At, double2 *M, StackConsts *consts,
                                                     uint32_t *queue, unsigned long long *work)
 {
     __shared__ double red[256];
@@ -31,6 +31,10 @@ __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, con
     for (int idx = tid; idx < rows * l_pad; idx += bd) {
         const int r = idx / l_pad, c = idx % l_pad;
         Ap[idx] = (r < n && c < l) ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
+    }
+    for (int idx = tid; idx < l_pad * n; idx += bd) {  // transposed copy (column reads coalesce)
+        const int c = idx / n, r = idx % n;
+        At[idx] = c < l ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
     }
     double cm = 0.0;
     for (int c = tid; c < l; c += bd) {
@@ -142,11 +146,11 @@ bool fista_a_fits_lds(int n, int l_pad, int waves, int zb)
     return fista_lds_bytes(n, l_pad, waves, zb, true) <= (size_t)160 * 1024 * waves / 4;
 }
 
-hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, double2 *gram,
+hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, float2 *At, double2 *gram,
                         StackConsts *consts, uint32_t *queue, unsigned long long *work,
                         hipStream_t s)
 {
-    hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, s, n, l, l_pad, A, Ap, gram, consts,
+    hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, s, n, l, l_pad, A, Ap, At, gram, consts,
                        queue, work);
     return hipGetLastError();
 }

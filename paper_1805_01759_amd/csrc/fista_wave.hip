@@ -55,6 +55,9 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
     float2 *R = D + l;        // r_k (n)
     float2 *Rp = R + n;       // r_{k-1}
     float2 *W = Rp + n;       // A d
+    // lanes per row of the forward product: 64 / (rows handled per pass)
+    const int rows_per_pass = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
+    const int rpl = 64 / rows_per_pass;
     const float lf = (float)a.consts->lf;
     const float inv_lf = (float)(1.0 / a.consts->lf);
     const float alpha0 = (float)a.consts->alpha0;
@@ -132,18 +135,28 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
                 d2 = wsumf(d2);
                 dl1 = wsumf(dl1);
                 WAVE_SYNC();
-                // w = A d (lanes over n)
+                // w = A d: lanes over rows (rpl lanes per row when N is small, each
+                // taking every rpl-th column), A read through its transposed copy so
+                // that the lanes' loads are contiguous
                 float w2 = 0.0f;
-                for (int i = lane; i < n; i += 64) {
+                for (int i0 = 0; i0 < n; i0 += rows_per_pass) {
+                    const int i = i0 + lane % rows_per_pass, part = lane / rows_per_pass;
                     float wr = 0.0f, wi = 0.0f;
-                    const float2 *row = a.A + (size_t)i * ld;
-                    for (int j = 0; j < l; ++j) {
-                        const float2 av = row[j], dv = D[j];
-                        wr = fmaf(av.x, dv.x, fmaf(-av.y, dv.y, wr));
-                        wi = fmaf(av.x, dv.y, fmaf(av.y, dv.x, wi));
+                    if (i < n) {
+                        for (int j = part; j < l; j += rpl) {
+                            const float2 av = a.At[(size_t)j * n + i], dv = D[j];
+                            wr = fmaf(av.x, dv.x, fmaf(-av.y, dv.y, wr));
+                            wi = fmaf(av.x, dv.y, fmaf(av.y, dv.x, wi));
+                        }
                     }
-                    W[i] = make_float2(wr, wi);
-                    w2 += wr * wr + wi * wi;
+                    for (int o = rows_per_pass; o < 64; o <<= 1) {
+                        wr += __shfl_xor(wr, o, 64);
+                        wi += __shfl_xor(wi, o, 64);
+                    }
+                    if (i < n && part == 0) {
+                        W[i] = make_float2(wr, wi);
+                        w2 += wr * wr + wi * wi;
+                    }
                 }
                 w2 = wsumf(w2);
                 ++n_fwd;

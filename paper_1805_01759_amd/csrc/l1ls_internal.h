@@ -30,6 +30,7 @@ struct FistaArgs {
     int n, l, l_pad, waves;
     int64_t p;
     const float2 *A;          // packed: rows_pad_for(n) x l_pad, zero padded rows and columns
+    const float2 *At;         // transposed: l_pad x n (At[m n + i] = A[i][m])
     const float2 *B;          // p x n
     const float *lambda;
     int64_t lambda_stride;
@@ -87,7 +88,7 @@ struct PolishArgsDev {
 
 // Workspace layout for one stack.
 struct StackWorkspace {
-    size_t a_packed, consts, queue, work, status, iters, kkt32, polish_list, gram, total;
+    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, total;
 };
 StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
 
@@ -97,7 +98,7 @@ int lpad_for(int l);           // 8 KB W
 int zblocks_for(int n);
 int rows_pad_for(int n);       // rows of the packed A: N rounded up to 16
 
-hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, double2 *gram,
+hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, float2 *At, double2 *gram,
                         StackConsts *consts, uint32_t *queue, unsigned long long *work,
                         hipStream_t s);
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s);
