@@ -8,8 +8,8 @@
 //   Eq. (15) for quadratic f:  ||A d||^2 <= ||d||^2 / (2 alpha), else alpha *= C_alpha
 //   accept iff F(x-bar) - F(x^k) <= 0, formed from differences
 //   r_{k+1} = r(y) + w,  G_{k+1} = 2 A^H r_{k+1}
-// The pixel's state lives in LDS (one wave per workgroup); A is read from the
-// packed workspace copy (L2-resident: it is shared by every pixel).
+// One wave per pixel; A is read from the packed workspace copies (L2-resident:
+// it is shared by every pixel).
 #include "l1ls_internal.h"
 
 namespace l1ls {
@@ -42,19 +42,20 @@ __device__ __forceinline__ void cprox_w(float vr, float vi, float tau, float &o_
         __builtin_amdgcn_wave_barrier();     \
     } while (0)
 
+// The pixel's x^k, x^{k-1}, G_k, G_{k-1} live in registers: lane `lane` holds
+// bins m = lane + 64 c, c < NC (NC = 64-bin chunks, rounded up to an
+// instantiated count); d, the residuals and A d sit in LDS for the row-wise
+// forward product, so a pixel needs (l_pad + 3 N) x 8 bytes of LDS.
+template <int NC>
 __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
     const int n = a.n, l = a.l, ld = a.l_pad;
-    float2 *X = reinterpret_cast<float2 *>(smem);
-    float2 *Xp = X + l;
-    float2 *G = Xp + l;
-    float2 *Gp = G + l;
-    float2 *D = Gp + l;       // d = x-bar - y of the current trial
-    float2 *R = D + l;        // r_k (n)
-    float2 *Rp = R + n;       // r_{k-1}
-    float2 *W = Rp + n;       // A d
+    float2 *D = reinterpret_cast<float2 *>(smem);  // d = x-bar - y of the current trial (64 NC)
+    float2 *R = D + 64 * NC;                        // r_k (n)
+    float2 *Rp = R + n;                             // r_{k-1}
+    float2 *W = Rp + n;                             // A d
     // lanes per row of the forward product: 64 / (rows handled per pass)
     const int rows_per_pass = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
     const int rpl = 64 / rows_per_pass;
@@ -63,6 +64,27 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
     const float alpha0 = (float)a.consts->alpha0;
     const float afloor = inv_lf;
     unsigned long long n_fwd = 0, n_adj = 0;
+    float2 X[NC], Xp[NC], G[NC], Gp[NC];
+
+    // G = 2 A^H r for the lane's bins (bins >= l give 0: A is zero padded to l_pad)
+    auto adjoint = [&]() {
+        float gr[NC], gi[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gr[c] = gi[c] = 0.0f;
+        for (int i = 0; i < n; ++i) {
+            const float2 rv = R[i];
+            const float2 *row = a.A + (size_t)i * ld;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int j = lane + 64 * c;
+                const float2 av = j < ld ? row[j] : make_float2(0.0f, 0.0f);
+                gr[c] = fmaf(av.x, rv.x, fmaf(av.y, rv.y, gr[c]));
+                gi[c] = fmaf(av.x, rv.y, fmaf(-av.y, rv.x, gi[c]));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) G[c] = make_float2(2.0f * gr[c], 2.0f * gi[c]);
+    };
 
     for (;;) {
         uint32_t base = 0;
@@ -74,7 +96,8 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
         const bool bad = !(lam > 0.0f) || !isfinite(lam);
         if (bad) lam = 1.0f;
         const float2 *b = a.B + (size_t)pix * n;
-        for (int j = lane; j < l; j += 64) X[j] = Xp[j] = Gp[j] = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) X[c] = Xp[c] = Gp[c] = make_float2(0.0f, 0.0f);
         float bb = 0.0f;
         for (int i = lane; i < n; i += 64) {
             const float2 v = b[i];
@@ -83,18 +106,8 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
         }
         float Fk = wsumf(bb);
         WAVE_SYNC();
-        // G = 2 A^H r
-        for (int j = lane; j < l; j += 64) {
-            float gr = 0.0f, gi = 0.0f;
-            for (int i = 0; i < n; ++i) {
-                const float2 av = a.A[(size_t)i * ld + j], rv = R[i];
-                gr = fmaf(av.x, rv.x, fmaf(av.y, rv.y, gr));
-                gi = fmaf(av.x, rv.y, fmaf(-av.y, rv.x, gi));
-            }
-            G[j] = make_float2(2.0f * gr, 2.0f * gi);
-        }
+        adjoint();
         ++n_adj;
-        WAVE_SYNC();
         float alpha = alpha0;
         int k = 1;
         float kkt = 0.0f;
@@ -102,8 +115,9 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
         for (;;) {
             // natural KKT residual at x^k with G_k
             float kmax = 0.0f;
-            for (int j = lane; j < l; j += 64) {
-                const float2 x = X[j], g = G[j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const float2 x = X[c], g = G[c];
                 float p_r, p_i;
                 cprox_w(x.x - g.x * inv_lf, x.y - g.y * inv_lf, lam * inv_lf, p_r, p_i);
                 const float e_r = x.x - p_r, e_i = x.y - p_i;
@@ -119,14 +133,15 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
                 const float tau = alpha * lam;
                 d2 = 0.0f;
                 dl1 = 0.0f;
-                for (int j = lane; j < l; j += 64) {
-                    const float2 x = X[j], xp = Xp[j], g = G[j], gp = Gp[j];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const float2 x = X[c], xp = Xp[c], g = G[c], gp = Gp[c];
                     const float y_r = x.x + beta * (x.x - xp.x), y_i = x.y + beta * (x.y - xp.y);
                     const float gy_r = g.x + beta * (g.x - gp.x), gy_i = g.y + beta * (g.y - gp.y);
                     float xb_r, xb_i;
                     cprox_w(y_r - alpha * gy_r, y_i - alpha * gy_i, tau, xb_r, xb_i);
                     const float d_r = xb_r - y_r, d_i = xb_i - y_i;
-                    D[j] = make_float2(d_r, d_i);
+                    D[lane + 64 * c] = make_float2(d_r, d_i);
                     d2 += d_r * d_r + d_i * d_i;
                     const float den = sqrtf(xb_r * xb_r + xb_i * xb_i) + sqrtf(x.x * x.x + x.y * x.y);
                     const float num = (xb_r - x.x) * (xb_r + x.x) + (xb_i - x.y) * (xb_i + x.y);
@@ -169,10 +184,14 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
                     const float rho = d2 / (2.0f * w2);
                     float an = alpha;
                     while (an > rho && an > afloor) an = fmaxf(a.c_alpha * an, afloor);
-                    const float c = an / alpha;
-                    for (int j = lane; j < l; j += 64) D[j] = make_float2(D[j].x * c, D[j].y * c);
-                    for (int i = lane; i < n; i += 64) W[i] = make_float2(W[i].x * c, W[i].y * c);
-                    dl1 *= c;
+                    const float cs = an / alpha;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const float2 dv = D[lane + 64 * c];
+                        D[lane + 64 * c] = make_float2(dv.x * cs, dv.y * cs);
+                    }
+                    for (int i = lane; i < n; i += 64) W[i] = make_float2(W[i].x * cs, W[i].y * cs);
+                    dl1 *= cs;
                     alpha = an;
                     WAVE_SYNC();
                     break;
@@ -194,31 +213,25 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
                 if (accept)
                     R[i] = make_float2(r.x + beta * (r.x - rp.x) + w.x, r.y + beta * (r.y - rp.y) + w.y);
             }
-            for (int j = lane; j < l; j += 64) {
-                const float2 x = X[j], xp = Xp[j], d = D[j];
-                Xp[j] = x;
-                Gp[j] = G[j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const float2 x = X[c], xp = Xp[c], d = D[lane + 64 * c];
+                Xp[c] = x;
+                Gp[c] = G[c];
                 if (accept)
-                    X[j] = make_float2(x.x + beta * (x.x - xp.x) + d.x, x.y + beta * (x.y - xp.y) + d.y);
+                    X[c] = make_float2(x.x + beta * (x.x - xp.x) + d.x, x.y + beta * (x.y - xp.y) + d.y);
             }
             if (accept) Fk += dF;
             ++k;
             WAVE_SYNC();
-            for (int j = lane; j < l; j += 64) {
-                float gr = 0.0f, gi = 0.0f;
-                for (int i = 0; i < n; ++i) {
-                    const float2 av = a.A[(size_t)i * ld + j], rv = R[i];
-                    gr = fmaf(av.x, rv.x, fmaf(av.y, rv.y, gr));
-                    gi = fmaf(av.x, rv.y, fmaf(-av.y, rv.x, gi));
-                }
-                G[j] = make_float2(2.0f * gr, 2.0f * gi);
-            }
+            adjoint();
             ++n_adj;
-            WAVE_SYNC();
         }
         // retire
         float2 *xo = a.X + (size_t)pix * l;
-        for (int j = lane; j < l; j += 64) xo[j] = X[j];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (lane + 64 * c < l) xo[lane + 64 * c] = X[c];
         if (lane == 0) {
             uint32_t st = 0;
             if (bad) st |= L1LS_PX_BAD_LAMBDA;
@@ -240,19 +253,25 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
     }
 }
 
-size_t fista_wave_lds(int n, int l) { return (size_t)(5 * l + 3 * n) * sizeof(float2); }
+// instantiated chunk counts (64 bins each) and the one used for l
+static int wave_chunks(int l)
+{
+    const int c = (l + 63) / 64;
+    const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int o : opts)
+        if (c <= o) return o;
+    return -1;
+}
 
-hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s)
+size_t fista_wave_lds(int n, int l) { return (size_t)(64 * wave_chunks(l) + 3 * n) * sizeof(float2); }
+
+template <int NC>
+static hipError_t launch_wave_nc(const FistaArgs &a, hipStream_t s)
 {
     const size_t lds = fista_wave_lds(a.n, a.l);
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipFuncSetAttribute((const void *)fista_wave_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_done = true;
-    }
+    auto kern = fista_wave_kernel<NC>;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fista_wave_kernel, 64, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     int dev = 0, cus = 0;
@@ -261,8 +280,23 @@ hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s)
     int64_t groups = (int64_t)per_cu * cus;
     if (groups > a.p) groups = a.p;
     if (groups < 1) groups = 1;
-    hipLaunchKernelGGL(fista_wave_kernel, dim3((unsigned)groups), dim3(64), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64), lds, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s)
+{
+    switch (wave_chunks(a.l)) {
+    case 1: return launch_wave_nc<1>(a, s);
+    case 2: return launch_wave_nc<2>(a, s);
+    case 3: return launch_wave_nc<3>(a, s);
+    case 4: return launch_wave_nc<4>(a, s);
+    case 6: return launch_wave_nc<6>(a, s);
+    case 8: return launch_wave_nc<8>(a, s);
+    case 12: return launch_wave_nc<12>(a, s);
+    case 16: return launch_wave_nc<16>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace l1ls
