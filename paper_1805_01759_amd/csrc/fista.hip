@@ -13,29 +13,51 @@ size_t fm_bf_planes_bytes_host(int rows, int l_pad);
 __device__ __forceinline__ int rows_pad_for_dev(int n) { return 16 * ((n + 15) / 16); }
 
 // ---------------------------------------------------------------------------
-// Setup: pack A (zero-padded rows to a multiple of 16, zero-padded columns), alpha0 = 1/(2 max_l ||a_l||^2),
-// L_f = 2 lambda_max(A A^H) by FP64 power iteration on the Gram matrix, and
-// reset the work queue.  One workgroup of 256 threads.
-__global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, const float2 *A,
-                                                    float2 *Ap, float2 *At, double2 *M, StackConsts *consts,
-                                                    uint32_t *queue, unsigned long long *work)
+// Setup, three launches on the caller's stream:
+//   setup_pack_kernel   (grid)    A packed zero-padded to rows_pad_for(n) x l_pad, and
+//                                 its transpose l_pad x n
+//   setup_gram_kernel   (grid)    FP64 Gram M = A A^H, one entry per thread
+//   setup_power_kernel  (1 group) queue/counter reset, alpha0 = 1/(2 max_l ||a_l||^2),
+//                                 L_f = 2 lambda_max(M) by FP64 power iteration
+__global__ void __launch_bounds__(256) setup_pack_kernel(int n, int l, int l_pad, const float2 *A,
+                                                         float2 *Ap, float2 *At)
 {
-    __shared__ double red[256];
+    const int rows = rows_pad_for_dev(n);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)rows * l_pad; idx += stride) {
+        const int r = (int)(idx / l_pad), c = (int)(idx % l_pad);
+        Ap[idx] = (r < n && c < l) ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
+    }
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)l_pad * n; idx += stride) {
+        const int c = (int)(idx / n), r = (int)(idx % n);  // transposed copy (column reads coalesce)
+        At[idx] = c < l ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
+    }
+}
+
+__global__ void __launch_bounds__(256) setup_gram_kernel(int n, int l, const float2 *A, double2 *M)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int i = e / n, kk = e % n;
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < l; ++c) {
+        const float2 p = A[(size_t)i * l + c], q = A[(size_t)kk * l + c];
+        sr += (double)p.x * q.x + (double)p.y * q.y;  // p conj(q)
+        si += (double)p.y * q.x - (double)p.x * q.y;
+    }
+    M[e] = make_double2(sr, si);
+}
+
+__global__ void __launch_bounds__(256) setup_power_kernel(int n, int l, const float2 *A, const double2 *M,
+                                                          StackConsts *consts, uint32_t *queue,
+                                                          unsigned long long *work)
+{
+    __shared__ double red[3][256];
     __shared__ double2 v[kMaxN];
     __shared__ double2 wv[kMaxN];
-    __shared__ double ctl[4];
     const int tid = threadIdx.x, bd = blockDim.x;
     if (tid < 4) queue[tid] = 0u;
     if (tid < 4) work[tid] = 0ull;
-    const int rows = rows_pad_for_dev(n);
-    for (int idx = tid; idx < rows * l_pad; idx += bd) {
-        const int r = idx / l_pad, c = idx % l_pad;
-        Ap[idx] = (r < n && c < l) ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
-    }
-    for (int idx = tid; idx < l_pad * n; idx += bd) {  // transposed copy (column reads coalesce)
-        const int c = idx / n, r = idx % n;
-        At[idx] = c < l ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
-    }
     double cm = 0.0;
     for (int c = tid; c < l; c += bd) {
         double s = 0.0;
@@ -45,34 +67,20 @@ __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, con
         }
         cm = fmax(cm, s);
     }
-    red[tid] = cm;
+    red[0][tid] = cm;
     __syncthreads();
     for (int s = bd / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+        if (tid < s) red[0][tid] = fmax(red[0][tid], red[0][tid + s]);
         __syncthreads();
     }
-    const double colmax = red[0];
-    __syncthreads();
-    // Gram M = A A^H (FP64), row-major n x n
-    for (int e = tid; e < n * n; e += bd) {
-        const int i = e / n, kk = e % n;
-        double sr = 0.0, si = 0.0;
-        for (int c = 0; c < l; ++c) {
-            const float2 p = A[(size_t)i * l + c], q = A[(size_t)kk * l + c];
-            sr += (double)p.x * q.x + (double)p.y * q.y;  // p conj(q)
-            si += (double)p.y * q.x - (double)p.x * q.y;
-        }
-        M[e] = make_double2(sr, si);
-    }
-    __threadfence_block();
+    const double colmax = red[0][0];
     __syncthreads();
     if (tid < n) v[tid] = make_double2(1.0 + 0.01 * tid, 0.001 * tid);
-    if (tid == 0) { ctl[0] = 0.0; ctl[1] = 0.0; }
     __syncthreads();
     int it;
     double lam_prev = -1.0;
     for (it = 0; it < 4000; ++it) {
-        // w = M v ; rayleigh = v^H M v / v^H v ; v = w / ||w||
+        // w = M v ; Rayleigh quotient v^H M v / v^H v ; v = w / ||w||  (one fused reduction)
         double pr = 0.0, nv = 0.0, nw = 0.0;
         if (tid < n) {
             double sr = 0.0, si = 0.0;
@@ -86,32 +94,20 @@ __global__ void __launch_bounds__(256) setup_kernel(int n, int l, int l_pad, con
             nv = v[tid].x * v[tid].x + v[tid].y * v[tid].y;
             nw = sr * sr + si * si;
         }
-        // three block sums
-        red[tid] = pr;
+        red[0][tid] = pr;
+        red[1][tid] = nv;
+        red[2][tid] = nw;
         __syncthreads();
         for (int s = bd / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
+            if (tid < s) {
+                red[0][tid] += red[0][tid + s];
+                red[1][tid] += red[1][tid + s];
+                red[2][tid] += red[2][tid + s];
+            }
             __syncthreads();
         }
-        const double rq_num = red[0];
-        __syncthreads();
-        red[tid] = nv;
-        __syncthreads();
-        for (int s = bd / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        const double vv = red[0];
-        __syncthreads();
-        red[tid] = nw;
-        __syncthreads();
-        for (int s = bd / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        const double ww = red[0];
-        __syncthreads();
-        const double lam_est = rq_num / vv;
+        const double lam_est = red[0][0] / red[1][0];
+        const double ww = red[2][0];
         const double inv = ww > 0.0 ? 1.0 / sqrt(ww) : 0.0;
         if (tid < n) v[tid] = make_double2(wv[tid].x * inv, wv[tid].y * inv);
         __syncthreads();
@@ -150,8 +146,16 @@ hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, fl
                         StackConsts *consts, uint32_t *queue, unsigned long long *work,
                         hipStream_t s)
 {
-    hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, s, n, l, l_pad, A, Ap, At, gram, consts,
-                       queue, work);
+    const int64_t elems = (int64_t)rows_pad_for(n) * l_pad;
+    int groups = (int)((elems + 255) / 256);
+    if (groups > 1024) groups = 1024;
+    hipLaunchKernelGGL(setup_pack_kernel, dim3(groups), dim3(256), 0, s, n, l, l_pad, A, Ap, At);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(setup_gram_kernel, dim3((n * n + 255) / 256), dim3(256), 0, s, n, l, A, gram);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(setup_power_kernel, dim3(1), dim3(256), 0, s, n, l, A, gram, consts, queue, work);
     return hipGetLastError();
 }
 
