@@ -35,8 +35,10 @@ WORKLOADS = {
 # sources of each timed kernel; a traffic record is used only while they are unchanged
 KERNEL_SOURCES = {
     "fista_mfma_kernel": ("fista_mfma.h", "fista.hip"),
+    "fista_mfma_kernel_bf16": ("fista_mfma.h", "fista.hip"),
     "fista_kernel": ("fista_impl.h", "fista.hip"),
-    "polish_kernel": ("polish.hip",),
+    "polish_kernel": ("polish.hip", "wave_reduce.h"),
+    "certify_kernel": ("certify.hip", "wave_reduce.h"),
 }
 PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
 
@@ -244,7 +246,7 @@ def main():
     fwd, adj, npol, pflops = api.solve_counters(n, l, p, d)
     avg_s = {kc: (ms / max(c, 1)) / 1e3 for kc, (ms, c) in kt.items()}
     # iteration kernel: algorithmic flops = (forward + adjoint products) x 8 N L
-    it_kernel = "fista_mfma_kernel" if args.precision == "fp32" else "fista_kernel"
+    it_kernel = "fista_mfma_kernel" if args.precision == "fp32" else "fista_mfma_kernel_bf16"
     it_flops = (fwd + adj) * 8.0 * n * l
     it_ach = it_flops / avg_s["iteration"]
     roof_it = {"bound": "mfma", "achieved": it_ach / 1e12, "peak": PEAK[args.precision] / 1e12,
@@ -285,6 +287,30 @@ def main():
         rec["roofline_iteration"] = roof_it
     elif args.polish and avg_s["refine"] > 0:
         rec["roofline_refine"] = roof_rf
+    # the metric compares the two contraction precisions: time the other one on the
+    # same stack and steps
+    other = "split_bf16" if args.precision == "fp32" else "fp32"
+    o_opts = dict(opts, precision=other)
+    for _ in range(args.warmup):
+        api.solve(Ad, Bd, ld, out=X, workspace=ws, **o_opts)
+    api.timing_enable(True)
+    for kc in ("iteration", "refine", "certify"):
+        api.timing_read(kc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    o_diags = []
+    for _ in range(args.steps):
+        _, d2 = api.solve(Ad, Bd, ld, out=X, workspace=ws, **o_opts)
+        o_diags.append(d2["status"])
+    torch.cuda.synchronize()
+    o_dt = time.perf_counter() - t0
+    o_kt = {kc: api.timing_read(kc) for kc in ("iteration", "refine", "certify")}
+    api.timing_enable(False)
+    o_solved = sum(int(((st & 1) != 0).sum().item()) for st in o_diags)
+    rec["compare"] = {"precision": other, "value": o_solved / o_dt, "unit": "pixels/s",
+                      "ms_per_step": o_dt / args.steps * 1e3,
+                      "solved_fraction": o_solved / (p * args.steps),
+                      "kernel_ms": {kc: (ms / max(c, 1)) for kc, (ms, c) in o_kt.items()}}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(A32, B32, l32, min(args.cpu_sample, p), args.max_iter, 1e-4)
     print(json.dumps(rec), flush=True)
