@@ -6,7 +6,7 @@ namespace l1ls {
 
 template <int NZB, int KB, bool ALDS, int PREC>
 hipError_t launch_one(const FistaArgs &a, int max_groups, hipStream_t s);
-template <int T, int KB, bool ALDS, int PREC>
+template <int T, int KB, bool ALDS, int PREC, int WMAX>
 hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s);
 size_t fm_bf_planes_bytes_host(int rows, int l_pad);
 
@@ -201,21 +201,33 @@ size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precisi
     return off;
 }
 
-// one wave per SIMD: a workgroup of W waves may use W/4 of the CU's 160 KB
+// Up to one wave per SIMD: a workgroup of W <= 4 waves may use W/4 of the CU's
+// 160 KB; a workgroup of more waves holds the whole CU.
 static bool mfma_lds_fits(const FistaArgs &a, int precision)
 {
-    return fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, true, precision) <= (size_t)160 * 1024 * a.waves / 4;
+    const size_t cap = (size_t)160 * 1024 * (a.waves < 4 ? a.waves : 4) / 4;
+    return fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, true, precision) <= cap;
 }
 
 template <int T>
 static hipError_t launch_mfma_t(const FistaArgs &a, int max_groups, hipStream_t s)
 {
+    if constexpr (T <= 2) {
+        if (slice_blocks_for(a.l) == 8) {
+            // 32 unknowns per wave, up to eight waves: the state of a 16-pixel tile
+            // fits two waves per SIMD without accumulation-register traffic
+            FistaArgs b = a;
+            b.waves = a.l_pad / 32;
+            return mfma_lds_fits(b, L1LS_FP32) ? launch_mfma_one<T, 2, true, L1LS_FP32, 8>(b, max_groups, s)
+                                               : launch_mfma_one<T, 2, false, L1LS_FP32, 8>(b, max_groups, s);
+        }
+    }
     const bool lds = mfma_lds_fits(a, L1LS_FP32);
     if (slice_blocks_for(a.l) == 8)
-        return lds ? launch_mfma_one<T, 4, true, L1LS_FP32>(a, max_groups, s)
-                   : launch_mfma_one<T, 4, false, L1LS_FP32>(a, max_groups, s);
-    return lds ? launch_mfma_one<T, 8, true, L1LS_FP32>(a, max_groups, s)
-               : launch_mfma_one<T, 8, false, L1LS_FP32>(a, max_groups, s);
+        return lds ? launch_mfma_one<T, 4, true, L1LS_FP32, 4>(a, max_groups, s)
+                   : launch_mfma_one<T, 4, false, L1LS_FP32, 4>(a, max_groups, s);
+    return lds ? launch_mfma_one<T, 8, true, L1LS_FP32, 4>(a, max_groups, s)
+               : launch_mfma_one<T, 8, false, L1LS_FP32, 4>(a, max_groups, s);
 }
 
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s)
@@ -226,10 +238,10 @@ hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipSt
         // wave); otherwise the real-embedded kernel
         if (slice_blocks_for(a.l) == 8 && mfma_lds_fits(a, L1LS_SPLIT_BF16)) {
             switch (T) {
-            case 1: return launch_mfma_one<1, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
-            case 2: return launch_mfma_one<2, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
-            case 3: return launch_mfma_one<3, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
-            case 4: return launch_mfma_one<4, 4, true, L1LS_SPLIT_BF16>(a, max_groups, s);
+            case 1: return launch_mfma_one<1, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
+            case 2: return launch_mfma_one<2, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
+            case 3: return launch_mfma_one<3, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
+            case 4: return launch_mfma_one<4, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
             default: break;
             }
         }

@@ -150,8 +150,8 @@ __host__ __device__ inline size_t fm_bf_planes_bytes(int rows, int l_pad)
     return ((size_t)4 * rows * fm_bf_ldf(l_pad) + (size_t)4 * l_pad * fm_bf_lda(rows)) * sizeof(uint16_t);
 }
 
-template <int T, int KB, bool ALDS, int PREC>
-__global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
+template <int T, int KB, bool ALDS, int PREC, int WMAX>
+__global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a)
 {
     static_assert(PREC == L1LS_FP32 || ALDS, "split-BF16 stages its A planes in LDS");
     constexpr bool BF = PREC == L1LS_SPLIT_BF16;
@@ -238,53 +238,67 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
     float alpha = alpha0, lam = 1.0f, Fk = 0.0f;
     bool active = false, bad = false, qdone = false;
 
-    // ---- refill the slots in `mask` from the global queue (workgroup-uniform)
+    // ---- refill the slots in `mask` from the global queue (workgroup-uniform).
+    // A fresh slot's state is reset with per-lane selects rather than under a
+    // branch, so that the register state is not copied around a divergent join.
+    // G needs no reset (the next adjoint overwrites it); everything that enters
+    // an extrapolation, even with beta = 0, is cleared so that nothing non-finite
+    // of the previous pixel survives.
     auto refill = [&](uint32_t mask) {
         if (mask == 0) return;
-        if (qdone) {
-            if ((mask >> j) & 1u) { active = false; pix = -1; }
-            return;
-        }
-        const uint32_t nfree = __popc(mask);
-        __syncthreads();
-        if (tid == 0) sQ[0] = atomicAdd(a.queue, nfree);
-        __syncthreads();
-        const uint64_t base = sQ[0];
-        if (base + nfree >= (uint64_t)a.p) qdone = true;
-        if ((mask >> j) & 1u) {
+        const bool mine = (mask >> j) & 1u;
+        bool fresh = false;
+        if (!qdone) {
+            const uint32_t nfree = __popc(mask);
+            __syncthreads();
+            if (tid == 0) sQ[0] = atomicAdd(a.queue, nfree);
+            __syncthreads();
+            const uint64_t base = sQ[0];
+            if (base + nfree >= (uint64_t)a.p) qdone = true;
             const uint64_t np = base + (uint64_t)__popc(mask & ((1u << j) - 1u));
-            if (np < (uint64_t)a.p) {
-                pix = (int64_t)np;
-                active = true;
-                k = 1;
-                alpha = alpha0;
-                lam = a.lambda[pix * a.lambda_stride];
-                bad = !(lam > 0.0f) || !isfinite(lam);
-                if (bad) lam = 1.0f;
-#pragma unroll
-                for (int b = 0; b < KB; ++b)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        Xr[b][q] = Xi[b][q] = Xpr[b][q] = Xpi[b][q] = Gr[b][q] = Gi[b][q] =
-                            Gpr[b][q] = Gpi[b][q] = AX[b][q] = 0.0f;
-                float bb = 0.0f;
-                const float2 *Bp = a.B + (size_t)pix * n;
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int nn = 16 * t + 4 * h + q;
-                        const float2 v = nn < n ? Bp[nn] : make_float2(0.0f, 0.0f);
-                        Rr[t][q] = Rpr[t][q] = -v.x;
-                        Ri[t][q] = Rpi[t][q] = -v.y;
-                        bb = fmaf(v.x, v.x, fmaf(v.y, v.y, bb));
-                    }
-                Fk = fm::sum_h(bb);
-            } else {
-                active = false;
-                pix = -1;
-            }
+            fresh = mine && np < (uint64_t)a.p;
+            if (fresh) pix = (int64_t)np;
         }
+        if (mine && !fresh) {
+            active = false;
+            pix = -1;
+        }
+        if (fresh) {
+            active = true;
+            k = 1;
+            alpha = alpha0;
+            lam = a.lambda[pix * a.lambda_stride];
+            bad = !(lam > 0.0f) || !isfinite(lam);
+            if (bad) lam = 1.0f;
+        }
+#pragma unroll
+        for (int b = 0; b < KB; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Xr[b][q] = fresh ? 0.0f : Xr[b][q];
+                Xi[b][q] = fresh ? 0.0f : Xi[b][q];
+                Xpr[b][q] = fresh ? 0.0f : Xpr[b][q];
+                Xpi[b][q] = fresh ? 0.0f : Xpi[b][q];
+                Gpr[b][q] = fresh ? 0.0f : Gpr[b][q];
+                Gpi[b][q] = fresh ? 0.0f : Gpi[b][q];
+                AX[b][q] = fresh ? 0.0f : AX[b][q];
+            }
+        float bb = 0.0f;
+        const float2 *Bp = a.B + (size_t)(fresh ? pix : 0) * n;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int nn = 16 * t + 4 * h + q;
+                const float2 v = fresh && nn < n ? Bp[nn] : make_float2(0.0f, 0.0f);
+                Rr[t][q] = fresh ? -v.x : Rr[t][q];
+                Ri[t][q] = fresh ? -v.y : Ri[t][q];
+                Rpr[t][q] = fresh ? -v.x : Rpr[t][q];
+                Rpi[t][q] = fresh ? -v.y : Rpi[t][q];
+                bb = fmaf(v.x, v.x, fmaf(v.y, v.y, bb));
+            }
+        bb = fm::sum_h(bb);
+        if (fresh) Fk = bb;
     };
 
     // ---- G = 2 A^H r for the wave's unknowns (all slots)
@@ -657,11 +671,12 @@ __global__ void __launch_bounds__(256) fista_mfma_kernel(const FistaArgs a)
 
 
 
-template <int T, int KB, bool ALDS, int PREC>
+template <int T, int KB, bool ALDS, int PREC, int WMAX>
 hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s)
 {
+    if (a.waves < 1 || a.waves > WMAX || a.waves * 16 * KB != a.l_pad) return hipErrorInvalidConfiguration;
     const size_t lds = fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, ALDS, PREC);
-    auto kern = fista_mfma_kernel<T, KB, ALDS, PREC>;
+    auto kern = fista_mfma_kernel<T, KB, ALDS, PREC, WMAX>;
     static bool attr_done = false;  // per instantiation
     if (!attr_done) {
         hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
