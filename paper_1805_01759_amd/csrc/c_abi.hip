@@ -220,6 +220,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         pa.X = (float2 *)X;
         pa.consts = consts;
         pa.count = queue + 1;
+        pa.next = queue + 2;
         pa.list = plist;
         pa.status = status_ws;
         pa.rounds = 64;

@@ -78,6 +78,7 @@ struct PolishArgsDev {
     float2 *X;
     const StackConsts *consts;
     const uint32_t *count;    // number of listed pixels
+    uint32_t *next;           // next list entry to take (zero before the launch)
     const int32_t *list;      // pixel indices
     uint32_t *status;         // workspace status: POLISHED is or-ed in
     unsigned long long *work; // [2] accumulates the refinement's FP64 flops

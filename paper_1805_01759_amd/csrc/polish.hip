@@ -17,11 +17,20 @@
 // until the KKT residual is at the target or no violator is left.  The point
 // with the least objective is kept and written back (complex64).
 //
-// LDS holds the best point (complex64), the working set's columns A_S, the
-// residual and a packed lower-triangular Hessian; the dense iterate is never
-// materialised (a per-bin index into the working set stands in for it), which
-// keeps the footprint near 12 KB at N=25, L=256 so that many pixels are in
-// flight per CU.
+// The Gram G = A_S^H A_S is kept across Newton steps and updated only when the
+// working set changes (a row appended on entry, a row and column removed on a
+// drop), so a Newton matrix costs O(|S|^2) lookups.  Within a round a step
+// z += t d updates r = A_S z - b by t A_S d and A_S^H r by t G d, and the line
+// search evaluates phi(z + t d) - phi(z) from <r, A_S d> and ||A_S d||^2 in
+// O(|S|) per trial point; r and A_S^H r are formed afresh at each round start
+// and after a drop.
+//
+// LDS holds the working set's columns A_S, the residual, the Gram and a packed
+// lower-triangular Hessian (for systems too large for the register solver);
+// the point with the least objective so far lives in X itself, and the dense
+// iterate is never materialised (a per-bin index into the working set stands
+// in for it), which keeps the footprint near 12.5 KB at N=25, L=256 so that
+// twelve pixels are in flight per CU.  Pixels are taken from a shared counter.
 #include "l1ls_internal.h"
 #include "wave_reduce.h"
 
@@ -31,20 +40,28 @@ using wr::lane_value;
 using wr::wmax;
 using wr::wsum;
 
+// value of the float v held by lane i (i uniform across the wave)
+__device__ __forceinline__ float lane_value_f(float v, int i)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+
 constexpr int kMaxSupp = 16;          // Newton on at most 16 complex unknowns
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
 constexpr int kTri = kMaxM * (kMaxM + 1) / 2;
+constexpr int kGc = kMaxSupp * (kMaxSupp + 1) / 2;
 
 __device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }  // k <= i
 
 struct PolishShared {
     double2 *r;         // n: residual A x - b (dynamic LDS)
-    float2 *best;       // l_pad: best point so far / starting point (dynamic LDS)
+    double2 *w;         // n: A_S d of the current Newton direction (dynamic LDS)
     float2 *AS;         // n x kMaxSupp: columns of the working set (dynamic LDS)
     int16_t *nzl;       // l_pad: nonzero bins of the starting point (dynamic LDS)
     int8_t *sidx;       // l_pad: slot of bin m in the working set, or -1 (dynamic LDS)
     double H[kTri];     // packed lower triangle of the real Hessian / its Cholesky factor
-    double2 z[kMaxSupp], zt[kMaxSupp];
+    double2 Gc[kGc];    // packed lower triangle of the Gram G = A_S^H A_S (Hermitian)
+    double2 z[kMaxSupp], c[kMaxSupp];  // working-set point and A_S^H r
     double grd[kMaxM], dir[kMaxM], invd[kMaxM];
     int S[kMaxSupp];
     int cnt;
@@ -63,7 +80,7 @@ __device__ __forceinline__ double2 ASat(const PolishShared &sh, int n, int t)
 }
 
 // r = A x0 - b for the starting point (its nonzero bins listed first)
-__device__ void residual_start(const PolishArgsDev &a, PolishShared &sh, const float2 *b)
+__device__ void residual_start(const PolishArgsDev &a, PolishShared &sh, const float2 *b, const float2 *x0)
 {
     const int lane = threadIdx.x;
     if (lane == 0) sh.cnt = 0;
@@ -72,7 +89,7 @@ __device__ void residual_start(const PolishArgsDev &a, PolishShared &sh, const f
         const int m = m0 + lane;
         bool nz = false;
         if (m < a.l) {
-            const float2 v = sh.best[m];
+            const float2 v = x0[m];
             nz = v.x != 0.0f || v.y != 0.0f;
         }
         const uint64_t bal = __ballot(nz);
@@ -87,7 +104,7 @@ __device__ void residual_start(const PolishArgsDev &a, PolishShared &sh, const f
         double rr = -(double)b[nn].x, ri = -(double)b[nn].y;
         for (int q = 0; q < cnt; ++q) {
             const int m = sh.nzl[q];
-            const float2 xf = sh.best[m];
+            const float2 xf = x0[m];
             const double2 av = Aat(a, nn, m);
             rr += av.x * xf.x - av.y * xf.y;
             ri += av.x * xf.y + av.y * xf.x;
@@ -125,13 +142,13 @@ __device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, float2 b
 
 // Full FP64 pass at the current point (sh.r its residual): natural KKT
 // residual, objective, and the worst off-support violator of |g| <= lambda.
-// START: the point is the starting iterate in sh.best (its nonzero bins listed
+// START: the point is the starting iterate x0 (its nonzero bins listed
 // in sh.nzl[0..nnz)); else it is z on the working set (sh.sidx, s entries).
 // Magnitudes are compared squared; the prox scale (a square root and a
 // division) is formed only on lanes whose |v| passes the threshold.
 template <bool START>
-__device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, int s, int nnz, double lam,
-                          double lf, double inv_lf, double &F, double &kk, int &vidx)
+__device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2 *x0, int s, int nnz,
+                          double lam, double lf, double inv_lf, double &F, double &kk, int &vidx)
 {
     const int lane = threadIdx.x;
     double acc = 0.0, l1 = 0.0, km = 0.0, vbest = 0.0;
@@ -139,7 +156,7 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, int s, int n
     for (int nn = lane; nn < a.n; nn += 64) acc += sh.r[nn].x * sh.r[nn].x + sh.r[nn].y * sh.r[nn].y;
     if (START) {
         for (int q = lane; q < nnz; q += 64) {
-            const float2 v = sh.best[sh.nzl[q]];
+            const float2 v = x0[sh.nzl[q]];
             l1 += sqrt((double)v.x * v.x + (double)v.y * v.y);
         }
     } else {
@@ -190,7 +207,7 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, int s, int n
             if (m >= a.l) continue;
             double xr, xi;
             if (START) {
-                const float2 v = sh.best[m];
+                const float2 v = x0[m];
                 xr = v.x;
                 xi = v.y;
             } else {
@@ -231,19 +248,18 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, int s, int n
     vidx = best;
 }
 
-// Packed lower triangle of 2 realify(A_S^H A_S) + lambda blkdiag((I - u u^T)/|z|) + mu I.
-// G = A_S^H A_S is Hermitian, so only its entries t >= u are formed; lanes are
-// split into 64/E groups over the rows of A_S when those entries fit E lanes,
-// and the group partial sums are combined with shuffles.
-__device__ void build_hessian(const PolishArgsDev &a, PolishShared &sh, int s, double lam, double mu)
+// Gram entries G_tu = a_t^H a_u (t >= u) for the packed indices [e0, e1) into
+// sh.Gc.  Lanes are split into 64/E groups over the rows of A_S when the
+// entries fit E lanes, and the group partial sums are combined with shuffles.
+__device__ void gram_entries(const PolishArgsDev &a, PolishShared &sh, int e0, int e1)
 {
     const int lane = threadIdx.x;
-    const int ne = s * (s + 1) / 2;
+    const int ne = e1 - e0;
     const int E = ne <= 16 ? 16 : (ne <= 32 ? 32 : 64), G = 64 / E;
     const int q = lane / E;
-    for (int e0 = 0; e0 < ne; e0 += E) {
-        const int e = e0 + lane % E;
-        const bool act = e < ne;
+    for (int f0 = 0; f0 < ne; f0 += E) {
+        const int e = e0 + f0 + lane % E;
+        const bool act = e < e1;
         int t = 0;
         if (act)
             while ((t + 1) * (t + 2) / 2 <= e) ++t;
@@ -265,22 +281,83 @@ __device__ void build_hessian(const PolishArgsDev &a, PolishShared &sh, int s, d
             gr += __shfl_xor(gr, 32, 64);
             gi += __shfl_xor(gi, 32, 64);
         }
-        if (act && q == 0) {
-            double h00 = 2.0 * gr, h11 = 2.0 * gr, h10 = 2.0 * gi;
-            if (t == u) {
-                const double2 zv = sh.z[t];
-                const double az = sqrt(zv.x * zv.x + zv.y * zv.y), iz = 1.0 / az;
-                const double ur = zv.x * iz, ui = zv.y * iz;
-                h00 += lam * (1.0 - ur * ur) * iz + mu;
-                h11 += lam * (1.0 - ui * ui) * iz + mu;
-                h10 -= lam * ur * ui * iz;
-            } else {
-                sh.H[tri(u + s, t)] = -h10;  // 2 Im G[u][t] = -2 Im G[t][u]
-            }
-            sh.H[tri(t, u)] = h00;
-            sh.H[tri(t + s, u + s)] = h11;
-            sh.H[tri(t + s, u)] = h10;
+        if (act && q == 0) sh.Gc[e] = make_double2(gr, gi);
+    }
+    __syncthreads();
+}
+
+// Remove slot t from the packed Gram of order s (the rows and columns after it
+// move up by one).
+__device__ void gram_drop(PolishShared &sh, int s, int t)
+{
+    const int lane = threadIdx.x;
+    const int ne = (s - 1) * s / 2;
+    double2 v[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = lane + 64 * k;
+        v[k] = make_double2(0.0, 0.0);
+        if (e < ne) {
+            int i = 0;
+            while ((i + 1) * (i + 2) / 2 <= e) ++i;
+            const int j = e - i * (i + 1) / 2;
+            v[k] = sh.Gc[tri(i + (i >= t), j + (j >= t))];
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (lane + 64 * k < ne) sh.Gc[lane + 64 * k] = v[k];
+    __syncthreads();
+}
+
+// G_tu for any t, u < s from the packed lower triangle (G_ut = conj(G_tu)).
+__device__ __forceinline__ double2 gram_at(const PolishShared &sh, int t, int u)
+{
+    if (t >= u) return sh.Gc[tri(t, u)];
+    const double2 g = sh.Gc[tri(u, t)];
+    return make_double2(g.x, -g.y);
+}
+
+// Entry (i, k) of the real Newton matrix of order 2s,
+//   2 [[Re G, -Im G], [Im G, Re G]] + lambda blkdiag((I - u u^T)/|z|) + mu I,
+// index i < s the real and s + i the imaginary part of slot i.  (ur, ui, iz):
+// u and 1/|z| of slot ti of row i, as the caller holds them.
+__device__ __forceinline__ double hess_entry(const PolishShared &sh, int i, int k, int s, double lam,
+                                             double mu, double ur, double ui, double iz)
+{
+    const bool pi = i >= s, pk = k >= s;
+    const int ti = pi ? i - s : i, tk = pk ? k - s : k;
+    const double2 g = gram_at(sh, ti, tk);
+    double h = pi == pk ? 2.0 * g.x : (pi ? 2.0 * g.y : -2.0 * g.y);
+    if (ti == tk) {
+        if (pi == pk) h += lam * (1.0 - (pi ? ui * ui : ur * ur)) * iz + mu;
+        else h -= lam * ur * ui * iz;
+    }
+    return h;
+}
+
+// u = z/|z| and 1/|z| of slot t
+__device__ __forceinline__ void unit_of(const PolishShared &sh, int t, double &ur, double &ui, double &iz)
+{
+    const double2 zv = sh.z[t];
+    iz = 1.0 / sqrt(zv.x * zv.x + zv.y * zv.y);
+    ur = zv.x * iz;
+    ui = zv.y * iz;
+}
+
+// The packed Newton matrix of order 2s in sh.H (the factorisation in LDS).
+__device__ void build_hessian(PolishShared &sh, int s, double lam, double mu)
+{
+    const int lane = threadIdx.x;
+    const int m2 = 2 * s, ne = m2 * (m2 + 1) / 2;
+    for (int e = lane; e < ne; e += 64) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        const int k = e - i * (i + 1) / 2;
+        double ur, ui, iz;
+        unit_of(sh, i >= s ? i - s : i, ur, ui, iz);
+        sh.H[e] = hess_entry(sh, i, k, s, lam, mu, ur, ui, iz);
     }
     __syncthreads();
 }
@@ -336,21 +413,24 @@ __device__ double newton_dir(const PolishShared &sh, int m2)
     return v;
 }
 
-// The Newton system H d = -grd of order m2 <= NS solved in registers: lane
-// i < NS holds row i of H (the identity pads rows and columns m2..NS-1), a
-// right-looking Cholesky broadcasts each column with readlane, and both
-// substitutions run on the same registers: no LDS traffic or barrier inside.
+// The Newton system H d = -grd of order m2 = 2s <= NS solved in registers:
+// lane i < NS assembles row i of H from the cached Gram (the identity pads rows
+// and columns m2..NS-1), a right-looking Cholesky broadcasts each column with
+// readlane, and both substitutions run on the same registers: no barrier inside.
 // Returns false (wave-uniform) if H is not positive definite; lane i ends
 // holding d_i.
 template <int NS>
-__device__ bool newton_regs(const PolishShared &sh, int m2, double &d)
+__device__ bool newton_regs(const PolishShared &sh, int s, double lam, double mu, double &d)
 {
     const int lane = threadIdx.x;
+    const int m2 = 2 * s;
     double row[NS];
+    double ur = 0.0, ui = 0.0, iz = 0.0;
+    if (lane < m2) unit_of(sh, lane >= s ? lane - s : lane, ur, ui, iz);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         if (lane < m2 && k < m2)
-            row[k] = k <= lane ? sh.H[tri(lane, k)] : sh.H[tri(k, lane)];
+            row[k] = hess_entry(sh, lane, k, s, lam, mu, ur, ui, iz);
         else
             row[k] = k == lane ? 1.0 : 0.0;
     }
@@ -402,8 +482,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         unsigned char *p = dyn;
         sh.r = reinterpret_cast<double2 *>(p);
         p += (size_t)a.n * sizeof(double2);
-        sh.best = reinterpret_cast<float2 *>(p);
-        p += (size_t)a.l_pad * sizeof(float2);
+        sh.w = reinterpret_cast<double2 *>(p);
+        p += (size_t)a.n * sizeof(double2);
         sh.AS = reinterpret_cast<float2 *>(p);
         p += (size_t)a.n * kMaxSupp * sizeof(float2);
         sh.nzl = reinterpret_cast<int16_t *>(p);
@@ -419,7 +499,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
     // FP64 flops of the algorithm (wave-uniform): 8 per complex multiply-add
     unsigned long long fl = 0;
     const unsigned long long f8n = 8ull * (unsigned long long)a.n;
-    for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    // pixels are taken from a shared counter, so a workgroup that becomes
+    // resident late only finds what is left
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(a.next, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= count) break;
         const int64_t p = a.list[item];
         const float lam_f = a.lambda[p * a.lambda_stride];
         if (!(lam_f > 0.0f) || !isfinite(lam_f)) continue;
@@ -428,17 +514,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         const float2 b0 = lane < a.n ? b[lane] : make_float2(0.0f, 0.0f);
         const float2 b1 = lane + 64 < a.n ? b[lane + 64] : make_float2(0.0f, 0.0f);
         float2 *xo = a.X + (size_t)p * a.l;
-        for (int m = lane; m < a.l_pad; m += 64) {
-            sh.best[m] = m < a.l ? xo[m] : make_float2(0.0f, 0.0f);
-            sh.sidx[m] = -1;
-        }
+        for (int m = lane; m < a.l_pad; m += 64) sh.sidx[m] = -1;
         __syncthreads();
-        // objective and FP64 natural KKT residual of the starting point
-        residual_start(a, sh, b);
+        // objective and FP64 natural KKT residual of the starting point (the
+        // point with the least objective so far is kept in X itself)
+        residual_start(a, sh, b, xo);
         fl += f8n * (unsigned long long)(sh.cnt + a.l);
         double fbest, kk0;
         int vdummy;
-        full_pass<true>(a, sh, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
+        full_pass<true>(a, sh, xo, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
         __syncthreads();
         if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
         // -- working set: the local maxima of |x| (FISTA spreads one scatterer
@@ -448,10 +532,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         for (int m0 = 0; m0 < a.l; m0 += 64) {
             const int m = m0 + lane;
             bool pk = false;
+            float2 xv = make_float2(0.0f, 0.0f);
             if (m < a.l) {
-                const float2 xv = sh.best[m];
-                const float2 xl = m > 0 ? sh.best[m - 1] : make_float2(0.0f, 0.0f);
-                const float2 xr = m + 1 < a.l ? sh.best[m + 1] : make_float2(0.0f, 0.0f);
+                xv = xo[m];
+                const float2 xl = m > 0 ? xo[m - 1] : make_float2(0.0f, 0.0f);
+                const float2 xr = m + 1 < a.l ? xo[m + 1] : make_float2(0.0f, 0.0f);
                 const double mag = (double)xv.x * xv.x + (double)xv.y * xv.y;
                 const double ml = (double)xl.x * xl.x + (double)xl.y * xl.y;
                 const double mr = (double)xr.x * xr.x + (double)xr.y * xr.y;
@@ -465,13 +550,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                     const int q = __ffsll((unsigned long long)bits) - 1;
                     bits &= bits - 1;
                     const int mm = m0 + q;
-                    const float2 xf = sh.best[mm];
-                    const double2 xv = make_double2(xf.x, xf.y);
-                    const double mag = xv.x * xv.x + xv.y * xv.y;
+                    const double2 xq = make_double2(lane_value_f(xv.x, q), lane_value_f(xv.y, q));
+                    const double mag = xq.x * xq.x + xq.y * xq.y;
                     const int s = sh.cnt;
                     if (s < kMaxSupp) {
                         sh.S[s] = mm;
-                        sh.z[s] = xv;
+                        sh.z[s] = xq;
                         sh.cnt = s + 1;
                     } else {
                         int wi = 0;
@@ -482,7 +566,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                         }
                         if (mag > wm) {
                             sh.S[wi] = mm;
-                            sh.z[wi] = xv;
+                            sh.z[wi] = xq;
                         }
                     }
                 }
@@ -492,27 +576,37 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         // ... and the larger neighbour of each peak (the exact solution of an
         // off-grid scatterer usually sits on two adjacent bins; seeding both saves
         // the round that would admit the second as a violator)
-        if (lane == 0) {
+        {
+            // lane t < np reads the neighbours of peak t; lane 0 appends them in order
             const int np = sh.cnt;
-            int cnt = np;
-            for (int t = 0; t < np && cnt < kMaxSupp; ++t) {
-                const int m = sh.S[t];
-                const float2 xl = m > 0 ? sh.best[m - 1] : make_float2(0.0f, 0.0f);
-                const float2 xr = m + 1 < a.l ? sh.best[m + 1] : make_float2(0.0f, 0.0f);
+            int nb = -1;
+            float2 xn = make_float2(0.0f, 0.0f);
+            if (lane < np) {
+                const int m = sh.S[lane];
+                const float2 xl = m > 0 ? xo[m - 1] : make_float2(0.0f, 0.0f);
+                const float2 xr = m + 1 < a.l ? xo[m + 1] : make_float2(0.0f, 0.0f);
                 const double ml = (double)xl.x * xl.x + (double)xl.y * xl.y;
                 const double mr = (double)xr.x * xr.x + (double)xr.y * xr.y;
-                const int nb = ml >= mr ? m - 1 : m + 1;
                 const double mn = ml >= mr ? ml : mr;
-                if (!(mn > 0.0)) continue;
-                bool dup = false;
-                for (int u = 0; u < cnt; ++u) dup = dup || sh.S[u] == nb;
-                if (dup) continue;
-                const float2 xf = sh.best[nb];
-                sh.S[cnt] = nb;
-                sh.z[cnt] = make_double2(xf.x, xf.y);
-                ++cnt;
+                if (mn > 0.0) {
+                    nb = ml >= mr ? m - 1 : m + 1;
+                    xn = ml >= mr ? xl : xr;
+                }
             }
-            sh.cnt = cnt;
+            if (lane == 0) {
+                int cnt = np;
+                for (int t = 0; t < np && cnt < kMaxSupp; ++t) {
+                    const int nbt = __builtin_amdgcn_readlane(nb, t);
+                    if (nbt < 0) continue;
+                    bool dup = false;
+                    for (int u = 0; u < cnt; ++u) dup = dup || sh.S[u] == nbt;
+                    if (dup) continue;
+                    sh.S[cnt] = nbt;
+                    sh.z[cnt] = make_double2(lane_value_f(xn.x, t), lane_value_f(xn.y, t));
+                    ++cnt;
+                }
+                sh.cnt = cnt;
+            }
         }
         __syncthreads();
         int s = sh.cnt;
@@ -521,15 +615,19 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             sh.AS[nn * kMaxSupp + t] = a.A[(size_t)nn * a.l_pad + sh.S[t]];
         }
         __syncthreads();
+        gram_entries(a, sh, 0, s * (s + 1) / 2);
+        fl += f8n * (unsigned long long)(s * (s + 1) / 2);
         for (int round = 0; round < a.rounds; ++round) {
+            // r = A_S z - b, c = A_S^H r and phi are formed afresh at the start of a
+            // round and after a drop; a step z += t d updates them exactly as
+            // r += t A_S d, c += t G d, phi += the change the line search measured.
+            bool fresh = true;
+            double ph = 0.0;
             for (int it = 0; it < 50 && s > 0; ++it) {
                 const int m2 = 2 * s;
-                const double ph = phi_support(a, sh, b0, b1, sh.z, s, lam);
-                fl += 2ull * f8n * (unsigned long long)s;  // residual and gradient
-                // gradient of phi on the working set (real pairs); 4 lane groups
-                // over the rows of A_S
-                double gmax = 0.0;
-                {
+                if (fresh) {
+                    ph = phi_support(a, sh, b0, b1, sh.z, s, lam);
+                    // c = A_S^H r (4 lane groups over the rows of A_S)
                     const int t = lane & 15, q = lane >> 4;
                     double gr = 0.0, gi = 0.0;
                     if (t < s) {
@@ -544,17 +642,21 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                     gi += __shfl_xor(gi, 16, 64);
                     gr += __shfl_xor(gr, 32, 64);
                     gi += __shfl_xor(gi, 32, 64);
-                    if (t < s) {
-                        const double2 zv = sh.z[t];
-                        const double az = sqrt(zv.x * zv.x + zv.y * zv.y);
-                        gr = 2.0 * gr + lam * zv.x / az;
-                        gi = 2.0 * gi + lam * zv.y / az;
-                        if (q == 0) {
-                            sh.grd[t] = gr;
-                            sh.grd[t + s] = gi;
-                        }
-                        gmax = sqrt(gr * gr + gi * gi);
-                    }
+                    if (t < s && q == 0) sh.c[t] = make_double2(gr, gi);
+                    __syncthreads();
+                    fl += 2ull * f8n * (unsigned long long)s;
+                    fresh = false;
+                }
+                // gradient of phi on the working set (real pairs)
+                double gmax = 0.0;
+                if (lane < s) {
+                    const double2 zv = sh.z[lane], cv = sh.c[lane];
+                    const double iz = 1.0 / sqrt(zv.x * zv.x + zv.y * zv.y);
+                    const double gr = 2.0 * cv.x + lam * zv.x * iz;
+                    const double gi = 2.0 * cv.y + lam * zv.y * iz;
+                    sh.grd[lane] = gr;
+                    sh.grd[lane + s] = gi;
+                    gmax = sqrt(gr * gr + gi * gi);
                 }
                 gmax = wmax(gmax);
                 __syncthreads();
@@ -563,18 +665,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                 double mu = 0.0, dv = 0.0;
                 bool ok = false;
                 for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
-                    build_hessian(a, sh, s, lam, mu);
-                    fl += f8n * (unsigned long long)(s * (s + 1) / 2) +
-                          (unsigned long long)(m2 * m2 * m2 / 3 + 2 * m2 * m2);
+                    fl += (unsigned long long)(m2 * m2 * m2 / 3 + 2 * m2 * m2);
                     if (m2 <= 4) {
-                        ok = newton_regs<4>(sh, m2, dv);
+                        ok = newton_regs<4>(sh, s, lam, mu, dv);
                     } else if (m2 <= 6) {
-                        ok = newton_regs<6>(sh, m2, dv);
+                        ok = newton_regs<6>(sh, s, lam, mu, dv);
                     } else if (m2 <= 8) {
-                        ok = newton_regs<8>(sh, m2, dv);
+                        ok = newton_regs<8>(sh, s, lam, mu, dv);
                     } else if (m2 <= 10) {
-                        ok = newton_regs<10>(sh, m2, dv);
+                        ok = newton_regs<10>(sh, s, lam, mu, dv);
                     } else {
+                        build_hessian(sh, s, lam, mu);
                         ok = cholesky(sh, m2);
                         if (ok) dv = newton_dir(sh, m2);
                     }
@@ -613,47 +714,92 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                             sh.z[t] = sh.z[t + 1];
                         }
                     }
-                    __syncthreads();
+                    gram_drop(sh, s, drop);
                     --s;
+                    fresh = true;
                     continue;
                 }
                 const double slope = wsum(lane < m2 ? sh.grd[lane] * dv : 0.0);
+                // w = A_S d with <r, w> and ||w||^2: phi(z + t d) - phi(z) =
+                //   t (2 Re<r, w> + t ||w||^2) + lambda (||z + t d||_1 - ||z||_1)
+                double rw = 0.0, ww = 0.0;
+                for (int nn = lane; nn < a.n; nn += 64) {
+                    double wr_ = 0.0, wi_ = 0.0;
+#pragma unroll 4
+                    for (int t = 0; t < s; ++t) {
+                        const double2 av = ASat(sh, nn, t);
+                        const double dr = sh.dir[t], di = sh.dir[t + s];
+                        wr_ += av.x * dr - av.y * di;
+                        wi_ += av.x * di + av.y * dr;
+                    }
+                    sh.w[nn] = make_double2(wr_, wi_);
+                    const double2 rv = sh.r[nn];
+                    rw += rv.x * wr_ + rv.y * wi_;
+                    ww += wr_ * wr_ + wi_ * wi_;
+                }
+                rw = wsum(rw);
+                ww = wsum(ww);
+                fl += f8n * (unsigned long long)s;
                 if (-slope <= 1e-14 * ph) {
                     // predicted decrease below the rounding of phi: take the step, stop
                     for (int t = lane; t < s; t += 64)
                         sh.z[t] = make_double2(sh.z[t].x + sh.dir[t], sh.z[t].y + sh.dir[t + s]);
+                    for (int nn = lane; nn < a.n; nn += 64)
+                        sh.r[nn] = make_double2(sh.r[nn].x + sh.w[nn].x, sh.r[nn].y + sh.w[nn].y);
                     __syncthreads();
                     break;
                 }
                 // Armijo backtracking on phi
-                double step = 1.0;
+                double step = 1.0, delta = 0.0;
                 bool acc = false;
+                double az = 0.0;  // |z_t| of lane t
+                if (lane < s) az = sqrt(sh.z[lane].x * sh.z[lane].x + sh.z[lane].y * sh.z[lane].y);
                 for (int ls = 0; ls < 40; ++ls) {
-                    for (int t = lane; t < s; t += 64)
-                        sh.zt[t] = make_double2(sh.z[t].x + step * sh.dir[t], sh.z[t].y + step * sh.dir[t + s]);
-                    __syncthreads();
-                    const double pn = phi_support(a, sh, b0, b1, sh.zt, s, lam);
-                    fl += f8n * (unsigned long long)s;
-                    if (pn <= ph + 1e-4 * step * slope) { acc = true; break; }
+                    double dl1 = 0.0;
+                    if (lane < s) {
+                        const double nr = sh.z[lane].x + step * sh.dir[lane];
+                        const double ni = sh.z[lane].y + step * sh.dir[lane + s];
+                        dl1 = sqrt(nr * nr + ni * ni) - az;
+                    }
+                    delta = step * (2.0 * rw + step * ww) + lam * wsum(dl1);
+                    if (delta <= 1e-4 * step * slope) {
+                        acc = true;
+                        break;
+                    }
                     step *= 0.5;
                 }
                 if (!acc) break;
-                for (int t = lane; t < s; t += 64) sh.z[t] = sh.zt[t];
+                // z += t d, r += t w, c += t G d
+                if (lane < s) {
+                    double gdr = 0.0, gdi = 0.0;
+                    for (int u = 0; u < s; ++u) {
+                        const double2 g = gram_at(sh, lane, u);
+                        const double dr = sh.dir[u], di = sh.dir[u + s];
+                        gdr += g.x * dr - g.y * di;
+                        gdi += g.x * di + g.y * dr;
+                    }
+                    sh.c[lane] = make_double2(sh.c[lane].x + step * gdr, sh.c[lane].y + step * gdi);
+                    sh.z[lane] = make_double2(sh.z[lane].x + step * sh.dir[lane], sh.z[lane].y + step * sh.dir[lane + s]);
+                }
+                for (int nn = lane; nn < a.n; nn += 64)
+                    sh.r[nn] = make_double2(sh.r[nn].x + step * sh.w[nn].x, sh.r[nn].y + step * sh.w[nn].y);
+                fl += 8ull * (unsigned long long)(s * s);
+                ph += delta;
                 __syncthreads();
             }
             // the working set as the current point; its residual
             for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = (int8_t)t;
             __syncthreads();
-            phi_support(a, sh, b0, b1, sh.z, s, lam);
+            if (fresh) phi_support(a, sh, b0, b1, sh.z, s, lam);
             double F, kk;
             int vidx;
-            full_pass<false>(a, sh, s, 0, lam, lf, inv_lf, F, kk, vidx);
+            full_pass<false>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
             fl += f8n * (unsigned long long)(s + a.l);
             if (F <= fbest) {
                 fbest = F;
-                for (int m = lane; m < a.l_pad; m += 64) {
+                for (int m = lane; m < a.l; m += 64) {
                     const int t = sh.sidx[m];
-                    sh.best[m] = t >= 0 ? make_float2((float)sh.z[t].x, (float)sh.z[t].y) : make_float2(0.0f, 0.0f);
+                    xo[m] = t >= 0 ? make_float2((float)sh.z[t].x, (float)sh.z[t].y) : make_float2(0.0f, 0.0f);
                 }
             }
             __syncthreads();
@@ -686,8 +832,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             __syncthreads();
             if (sc == 0.0) break;
             ++s;
+            gram_entries(a, sh, (s - 1) * s / 2, s * (s + 1) / 2);  // the new row of G
+            fl += f8n * (unsigned long long)s;
         }
-        for (int m = lane; m < a.l; m += 64) xo[m] = sh.best[m];
         if (lane == 0) a.status[p] |= L1LS_PX_POLISHED;
         __syncthreads();
     }
@@ -696,7 +843,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
 
 size_t polish_lds_bytes(int n, int l_pad)
 {
-    return (size_t)n * sizeof(double2) + (size_t)l_pad * (sizeof(float2) + sizeof(int16_t) + sizeof(int8_t)) +
+    return (size_t)2 * n * sizeof(double2) + (size_t)l_pad * (sizeof(int16_t) + sizeof(int8_t)) +
            (size_t)n * kMaxSupp * sizeof(float2);
 }
 
