@@ -223,7 +223,7 @@ def main():
     ap.add_argument("--max-iter", type=int, default=500)
     ap.add_argument("--polish-after", type=int, default=20)
     ap.add_argument("--polish", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
