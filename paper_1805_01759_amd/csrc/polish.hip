@@ -62,6 +62,7 @@ struct PolishShared {
     double H[kTri];     // packed lower triangle of the real Hessian / its Cholesky factor
     double2 Gc[kGc];    // packed lower triangle of the Gram G = A_S^H A_S (Hermitian)
     double2 z[kMaxSupp], c[kMaxSupp];  // working-set point and A_S^H r
+    double ur[kMaxSupp], ui[kMaxSupp], iz[kMaxSupp];  // z/|z| and 1/|z| per slot
     double grd[kMaxM], dir[kMaxM], invd[kMaxM];
     int S[kMaxSupp];
     int cnt;
@@ -319,45 +320,32 @@ __device__ __forceinline__ double2 gram_at(const PolishShared &sh, int t, int u)
     return make_double2(g.x, -g.y);
 }
 
-// Entry (i, k) of the real Newton matrix of order 2s,
+// The packed Newton matrix of order m2 = 2s,
 //   2 [[Re G, -Im G], [Im G, Re G]] + lambda blkdiag((I - u u^T)/|z|) + mu I,
-// index i < s the real and s + i the imaginary part of slot i.  (ur, ui, iz):
-// u and 1/|z| of slot ti of row i, as the caller holds them.
-__device__ __forceinline__ double hess_entry(const PolishShared &sh, int i, int k, int s, double lam,
-                                             double mu, double ur, double ui, double iz)
-{
-    const bool pi = i >= s, pk = k >= s;
-    const int ti = pi ? i - s : i, tk = pk ? k - s : k;
-    const double2 g = gram_at(sh, ti, tk);
-    double h = pi == pk ? 2.0 * g.x : (pi ? 2.0 * g.y : -2.0 * g.y);
-    if (ti == tk) {
-        if (pi == pk) h += lam * (1.0 - (pi ? ui * ui : ur * ur)) * iz + mu;
-        else h -= lam * ur * ui * iz;
-    }
-    return h;
-}
-
-// u = z/|z| and 1/|z| of slot t
-__device__ __forceinline__ void unit_of(const PolishShared &sh, int t, double &ur, double &ui, double &iz)
-{
-    const double2 zv = sh.z[t];
-    iz = 1.0 / sqrt(zv.x * zv.x + zv.y * zv.y);
-    ur = zv.x * iz;
-    ui = zv.y * iz;
-}
-
-// The packed Newton matrix of order 2s in sh.H (the factorisation in LDS).
+// in sh.H, one entry per lane: index i < s is the real and s + i the imaginary
+// part of slot i; u and 1/|z| per slot come from sh.ur, sh.ui, sh.iz.
 __device__ void build_hessian(PolishShared &sh, int s, double lam, double mu)
 {
     const int lane = threadIdx.x;
     const int m2 = 2 * s, ne = m2 * (m2 + 1) / 2;
     for (int e = lane; e < ne; e += 64) {
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        // row i of packed index e: the root of i (i + 1) / 2 = e, then corrected
+        int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        if ((i + 1) * (i + 2) / 2 <= e) ++i;
+        if (i * (i + 1) / 2 > e) --i;
         const int k = e - i * (i + 1) / 2;
-        double ur, ui, iz;
-        unit_of(sh, i >= s ? i - s : i, ur, ui, iz);
-        sh.H[e] = hess_entry(sh, i, k, s, lam, mu, ur, ui, iz);
+        const bool pi = i >= s, pk = k >= s;
+        const int ti = pi ? i - s : i, tk = pk ? k - s : k;
+        const int hi = ti > tk ? ti : tk, lo = ti > tk ? tk : ti;
+        const double2 g = sh.Gc[tri(hi, lo)];
+        const double gy = ti >= tk ? g.y : -g.y;  // Im G[ti][tk]
+        double h = pi == pk ? 2.0 * g.x : (pi ? 2.0 * gy : -2.0 * gy);
+        if (ti == tk) {
+            const double ur = sh.ur[ti], ui = sh.ui[ti], iz = sh.iz[ti];
+            if (pi == pk) h += lam * (1.0 - (pi ? ui * ui : ur * ur)) * iz + mu;
+            else h -= lam * ur * ui * iz;
+        }
+        sh.H[e] = h;
     }
     __syncthreads();
 }
@@ -413,24 +401,21 @@ __device__ double newton_dir(const PolishShared &sh, int m2)
     return v;
 }
 
-// The Newton system H d = -grd of order m2 = 2s <= NS solved in registers:
-// lane i < NS assembles row i of H from the cached Gram (the identity pads rows
-// and columns m2..NS-1), a right-looking Cholesky broadcasts each column with
-// readlane, and both substitutions run on the same registers: no barrier inside.
+// The Newton system (H + mu I) d = -grd of order m2 <= NS solved in registers:
+// lane i < NS holds row i of H (the identity pads rows and columns m2..NS-1),
+// a right-looking Cholesky broadcasts each column with readlane, and both
+// substitutions run on the same registers: no LDS traffic or barrier inside.
 // Returns false (wave-uniform) if H is not positive definite; lane i ends
 // holding d_i.
 template <int NS>
-__device__ bool newton_regs(const PolishShared &sh, int s, double lam, double mu, double &d)
+__device__ bool newton_regs(const PolishShared &sh, int m2, double mu, double &d)
 {
     const int lane = threadIdx.x;
-    const int m2 = 2 * s;
     double row[NS];
-    double ur = 0.0, ui = 0.0, iz = 0.0;
-    if (lane < m2) unit_of(sh, lane >= s ? lane - s : lane, ur, ui, iz);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         if (lane < m2 && k < m2)
-            row[k] = hess_entry(sh, lane, k, s, lam, mu, ur, ui, iz);
+            row[k] = (k <= lane ? sh.H[tri(lane, k)] : sh.H[tri(k, lane)]) + (k == lane ? mu : 0.0);
         else
             row[k] = k == lane ? 1.0 : 0.0;
     }
@@ -656,6 +641,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                     const double gi = 2.0 * cv.y + lam * zv.y * iz;
                     sh.grd[lane] = gr;
                     sh.grd[lane + s] = gi;
+                    sh.ur[lane] = zv.x * iz;
+                    sh.ui[lane] = zv.y * iz;
+                    sh.iz[lane] = iz;
                     gmax = sqrt(gr * gr + gi * gi);
                 }
                 gmax = wmax(gmax);
@@ -664,16 +652,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                 // Newton direction; shifted retries while the Hessian is not PD
                 double mu = 0.0, dv = 0.0;
                 bool ok = false;
+                if (m2 <= 10) build_hessian(sh, s, lam, 0.0);
                 for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
                     fl += (unsigned long long)(m2 * m2 * m2 / 3 + 2 * m2 * m2);
                     if (m2 <= 4) {
-                        ok = newton_regs<4>(sh, s, lam, mu, dv);
+                        ok = newton_regs<4>(sh, m2, mu, dv);
                     } else if (m2 <= 6) {
-                        ok = newton_regs<6>(sh, s, lam, mu, dv);
+                        ok = newton_regs<6>(sh, m2, mu, dv);
                     } else if (m2 <= 8) {
-                        ok = newton_regs<8>(sh, s, lam, mu, dv);
+                        ok = newton_regs<8>(sh, m2, mu, dv);
                     } else if (m2 <= 10) {
-                        ok = newton_regs<10>(sh, s, lam, mu, dv);
+                        ok = newton_regs<10>(sh, m2, mu, dv);
                     } else {
                         build_hessian(sh, s, lam, mu);
                         ok = cholesky(sh, m2);
