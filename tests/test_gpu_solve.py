@@ -124,8 +124,14 @@ def test_orthonormal_columns_closed_form(dev):
     assert np.allclose(X.cpu().numpy(), want, atol=2e-6)
 
 
-@pytest.mark.parametrize("n,l,p", [(1, 1, 1), (3, 7, 17), (16, 64, 33), (17, 65, 50), (8, 200, 40),
-                                   (25, 256, 100), (40, 300, 20), (64, 512, 16)])
+# the shapes cover every iteration-kernel family: 32 unknowns per wave with 2-8
+# waves (N <= 32, L <= 256), 64 per wave (32 < N <= 64, L <= 256), 128 per wave
+# (256 < L <= 512), with ragged N, L and pixel counts
+RAGGED = [(1, 1, 1), (3, 7, 17), (16, 64, 33), (17, 65, 50), (8, 200, 40), (25, 256, 100),
+          (33, 129, 30), (40, 200, 24), (64, 256, 16), (40, 300, 20), (64, 512, 16)]
+
+
+@pytest.mark.parametrize("n,l,p", RAGGED)
 def test_ragged_shapes(dev, orc, n, l, p):
     geom = synth.make_geometry(9, n, l, 250.0, -50.0, 50.0)
     spec = synth.Spec(9, n, l, p, 250.0, -50.0, 50.0, "c1", 10.0)
@@ -226,6 +232,27 @@ def test_split_bf16_exact_mode(c1):
     conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
     assert conv.all()
     assert (e <= 1e-3).all()
+
+
+@pytest.mark.parametrize("n,l,p", [(3, 7, 17), (25, 256, 40), (40, 200, 24), (64, 256, 16), (50, 512, 12)])
+def test_split_bf16_ragged_shapes(dev, orc, n, l, p):
+    """Split-BF16 iteration on every kernel family it uses (bf16 planes in LDS for
+    L <= 256, the real-embedded form above), refined in FP64: objective at the
+    certified minimiser and every pixel converged."""
+    geom = synth.make_geometry(9, n, l, 250.0, -50.0, 50.0)
+    spec = synth.Spec(9, n, l, p, 250.0, -50.0, 50.0, "c1", 10.0)
+    B, lam = synth.make_pixels(spec, geom)
+    A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
+    Ad, Bd, ld = _to_dev(dev, A32, B32, l32)
+    X, d = api.solve(Ad, Bd, ld, fp64_polish=2, polish_after=100, precision="split_bf16")
+    A64, B64, L64 = _c128(A32, B32, l32)
+    Xe, de = orc.exact_batch(A64, B64, L64)
+    Xg = X.cpu().numpy().astype(np.complex128)
+    Fg = np.array([orc.objective(A64, B64[i], L64[i], Xg[i]) for i in range(p)])
+    gap = (Fg - de["objective"]) / np.maximum(de["objective"], 1.0)
+    conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
+    assert gap.max() <= 1e-9
+    assert conv.all()
 
 
 def test_close_pairs_sampled(dev, orc):
