@@ -403,12 +403,14 @@ __device__ double newton_dir(const PolishShared &sh, int m2)
 
 // The Newton system (H + mu I) d = -grd of order m2 <= NS solved in registers:
 // lane i < NS holds row i of H (the identity pads rows and columns m2..NS-1),
-// a right-looking Cholesky broadcasts each column with readlane, and both
-// substitutions run on the same registers: no LDS traffic or barrier inside.
+// a right-looking Cholesky broadcasts each column with readlane and keeps the
+// unit-diagonal factor U (L = U diag(L_jj)), so that both substitutions need one
+// broadcast per column and no selects; U is transposed once through LDS for
+// the backward substitution.
 // Returns false (wave-uniform) if H is not positive definite; lane i ends
 // holding d_i.
 template <int NS>
-__device__ bool newton_regs(const PolishShared &sh, int m2, double mu, double &d)
+__device__ bool newton_regs(PolishShared &sh, int m2, double mu, double &d)
 {
     const int lane = threadIdx.x;
     double row[NS];
@@ -419,7 +421,9 @@ __device__ bool newton_regs(const PolishShared &sh, int m2, double mu, double &d
         else
             row[k] = k == lane ? 1.0 : 0.0;
     }
-    double invl = 0.0;  // lane j: 1 / L_jj
+    // H = L L^T with L = U D, U unit lower, D = diag(L_jj): lane i keeps U_ij in
+    // row[j] below the diagonal (0 on and above it) and 1/L_ii in invl.
+    double invl = 0.0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         const double piv = lane_value(row[j], j);
@@ -430,30 +434,31 @@ __device__ bool newton_regs(const PolishShared &sh, int m2, double mu, double &d
         iv = iv * fma(-0.5 * piv, iv * iv, 1.5);
         if (lane == j) invl = iv;
         const double lj = row[j] * iv;  // lane i >= j: L_ij
-        row[j] = lj;
         const double act = lane > j ? lj : 0.0;
 #pragma unroll
         for (int k = j + 1; k < NS; ++k) row[k] -= act * lane_value(lj, k);  // - L_ij L_kj
+        row[j] = act * iv;  // U_ij
     }
-    // L y = -grd (lane i > j holds L_ij in row[j])
+    // U y' = -grd (unit diagonal: y'_j is final when its column is reached)
     double v = lane < m2 ? -sh.grd[lane] : 0.0;
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        const double yj = lane_value(v, j) * lane_value(invl, j);
-        if (lane == j) v = yj;
-        else if (lane > j) v -= row[j] * yj;
-    }
-    // L^T d = y (L_ji, i < j, is lane j's row[i], broadcast)
+    for (int j = 0; j < NS; ++j) v -= row[j] * lane_value(v, j);
+    // L y = -grd is y = D^-1 y', and L^T d = y is U^T d = D^-2 y'
+    v *= invl * invl;
+    // U^T d = w: U_ji (i < j) is lane j's row[i]; the factor is transposed through
+    // LDS (past the packed Hessian, which a retry with a shift still needs) so
+    // that lane i holds column i of U
+    double *T = sh.H + kTri - NS * NS;
+    if (lane < NS) {
 #pragma unroll
-    for (int j = NS - 1; j >= 0; --j) {
-        const double dj = lane_value(v, j) * lane_value(invl, j);
-        if (lane == j) v = dj;
-#pragma unroll
-        for (int i = 0; i < j; ++i) {
-            const double lji = lane_value(row[i], j);
-            if (lane == i) v -= lji * dj;
-        }
+        for (int k = 0; k < NS; ++k) T[lane * NS + k] = row[k];
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NS; ++k) row[k] = lane < NS ? T[k * NS + lane] : 0.0;  // U_ki
+#pragma unroll
+    for (int j = NS - 1; j >= 0; --j) v -= row[j] * lane_value(v, j);
+    __syncthreads();
     d = v;
     return true;
 }
