@@ -2,6 +2,9 @@
 // Eq. (1)); not part of the paper's method, it turns "KKT <= tol" into the
 // minimiser to FP64 accuracy and catches pixels the FP32 iteration left.
 //
+// A pixel whose FP32 KKT test passed is first checked in FP64 and skipped if it
+// is solved; one the FP32 stage capped is refined without that check.
+//
 // Per pixel (one 64-lane workgroup), starting from the working set S of the
 // local maxima of |x| of the FP32 iterate and the larger neighbour of each, repeat
 //   * damped Newton on phi(z) = ||A_S z - b||^2 + lambda sum |z_s| over the
@@ -509,12 +512,26 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         // objective and FP64 natural KKT residual of the starting point (the
         // point with the least objective so far is kept in X itself)
         residual_start(a, sh, b, xo);
-        fl += f8n * (unsigned long long)(sh.cnt + a.l);
-        double fbest, kk0;
-        int vdummy;
-        full_pass<true>(a, sh, xo, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
-        __syncthreads();
-        if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
+        fl += f8n * (unsigned long long)sh.cnt;
+        double fbest;
+        if (a.mode == 1 && (a.status[p] & L1LS_PX_MAX_ITER) != 0) {
+            // the FP32 stage's own KKT test failed: the pixel is refined, and only
+            // the objective of the starting point is needed
+            double acc = 0.0;
+            for (int nn = lane; nn < a.n; nn += 64) acc += sh.r[nn].x * sh.r[nn].x + sh.r[nn].y * sh.r[nn].y;
+            for (int q = lane; q < sh.cnt; q += 64) {
+                const float2 v = xo[sh.nzl[q]];
+                acc += lam * sqrt((double)v.x * v.x + (double)v.y * v.y);
+            }
+            fbest = wsum(acc);
+        } else {
+            double kk0;
+            int vdummy;
+            full_pass<true>(a, sh, xo, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
+            fl += f8n * (unsigned long long)a.l;
+            __syncthreads();
+            if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
+        }
         // -- working set: the local maxima of |x| (FISTA spreads one scatterer
         //    over neighbouring bins); at most kMaxSupp, the largest kept
         if (lane == 0) sh.cnt = 0;
