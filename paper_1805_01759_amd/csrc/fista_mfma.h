@@ -33,7 +33,8 @@
 // cancel), which is evaluated from the forward product of d.  The monotone
 // test is the sign of F(x-bar) - F(x^k) formed from differences:
 //   ||r-bar||^2 - ||r_k||^2 = <r-bar - r_k, r-bar + r_k>,
-//   ||x-bar||_1 - ||x^k||_1 = sum_m (|x-bar_m| - |x^k_m|)   (|x^k_m| kept per unknown).
+//   ||x-bar||_1 - ||x^k||_1 = sum_m (|x-bar_m| - |x^k_m|), |x-bar_m| from the prox.
+// The last trial's x-bar stays in registers for the acceptance.
 //
 // Split-BF16 (PREC = L1LS_SPLIT_BF16): every real product a.b is formed as
 // hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b) with x = hi(x) + lo(x), hi = RNE bf16 of x,
@@ -220,14 +221,14 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
 
     float Xr[KB][4], Xi[KB][4], Xpr[KB][4], Xpi[KB][4];
     float Gr[KB][4], Gi[KB][4], Gpr[KB][4], Gpi[KB][4];
-    float AX[KB][4];                                   // |x^k_m|
+    float XBr[KB][4], XBi[KB][4];                      // x-bar of the last trial
     float Rr[T][4], Ri[T][4], Rpr[T][4], Rpi[T][4];    // residual A x - b of x^k, x^{k-1}
 #pragma unroll
     for (int b = 0; b < KB; ++b)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             Xr[b][q] = Xi[b][q] = Xpr[b][q] = Xpi[b][q] = Gr[b][q] = Gi[b][q] = Gpr[b][q] =
-                Gpi[b][q] = AX[b][q] = 0.0f;
+                Gpi[b][q] = XBr[b][q] = XBi[b][q] = 0.0f;
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -281,7 +282,6 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
                 Xpi[b][q] = fresh ? 0.0f : Xpi[b][q];
                 Gpr[b][q] = fresh ? 0.0f : Gpr[b][q];
                 Gpi[b][q] = fresh ? 0.0f : Gpi[b][q];
-                AX[b][q] = fresh ? 0.0f : AX[b][q];
             }
         float bb = 0.0f;
         const float2 *Bp = a.B + (size_t)(fresh ? pix : 0) * n;
@@ -420,8 +420,10 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
                                   Gpr[b][q], Gpi[b][q], beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
                     dr[b][q] = xb_r - y_r;
                     di[b][q] = xb_i - y_i;
+                    XBr[b][q] = xb_r;
+                    XBi[b][q] = xb_i;
                     d2 = fmaf(dr[b][q], dr[b][q], fmaf(di[b][q], di[b][q], d2));
-                    s1 += axb - AX[b][q];
+                    s1 += axb - __builtin_amdgcn_sqrtf(fmaf(Xr[b][q], Xr[b][q], Xi[b][q] * Xi[b][q]));
                 }
             };
             if constexpr (!BF) {
@@ -575,6 +577,13 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
                     Wr[t] *= c;
                     Wi[t] *= c;
                 }
+#pragma unroll
+                for (int b = 0; b < KB; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        XBr[b][q] *= c;
+                        XBi[b][q] *= c;
+                    }
                 w2 *= c * c;
                 d2s *= c * c;
                 l1 *= c;
@@ -618,14 +627,10 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
             const float dF = fmaf(lam, l1, dfr);
             const bool live = active && !retire;
             const bool accept = live && (!a.monotone || dF <= 0.0f);
-            const float tau = alpha * lam;
 #pragma unroll
             for (int b = 0; b < KB; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    float y_r, y_i, xb_r, xb_i, axb;
-                    fm::trial_one(Xr[b][q], Xi[b][q], Xpr[b][q], Xpi[b][q], Gr[b][q], Gi[b][q],
-                                  Gpr[b][q], Gpi[b][q], beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
                     if (live) {
                         Xpr[b][q] = Xr[b][q];
                         Xpi[b][q] = Xi[b][q];
@@ -633,9 +638,8 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
                         Gpi[b][q] = Gi[b][q];
                     }
                     if (accept) {
-                        Xr[b][q] = xb_r;
-                        Xi[b][q] = xb_i;
-                        AX[b][q] = axb;
+                        Xr[b][q] = XBr[b][q];
+                        Xi[b][q] = XBi[b][q];
                     }
                 }
 #pragma unroll
