@@ -221,7 +221,7 @@ def main():
     ap.add_argument("--workload", default="scene", choices=sorted(WORKLOADS) + ["unrolled", "batched"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
     ap.add_argument("--max-iter", type=int, default=500)
-    ap.add_argument("--polish-after", type=int, default=16)
+    ap.add_argument("--polish-after", type=int, default=12)
     ap.add_argument("--polish", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
