@@ -486,8 +486,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
     __syncthreads();
     const double lf = a.consts->lf;
     const double inv_lf = 1.0 / lf;
-    const double gstop = a.mode == 2 ? 1e-13 : 1e-3 * (double)a.tol;
-    const double kstop = a.mode == 2 ? 1e-10 : 1e-2 * (double)a.tol;
+    const double gstop = a.mode == 2 ? 1e-13 : 1e-2 * (double)a.tol;
+    const double kstop = a.mode == 2 ? 1e-10 : 1e-1 * (double)a.tol;
     const uint32_t count = *a.count;
     // FP64 flops of the algorithm (wave-uniform): 8 per complex multiply-add
     unsigned long long fl = 0;
