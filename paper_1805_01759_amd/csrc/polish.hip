@@ -22,11 +22,11 @@
 //
 // The Gram G = A_S^H A_S is kept across Newton steps and updated only when the
 // working set changes (a row appended on entry, a row and column removed on a
-// drop), so a Newton matrix costs O(|S|^2) lookups.  Within a round a step
-// z += t d updates r = A_S z - b by t A_S d and A_S^H r by t G d, and the line
-// search evaluates phi(z + t d) - phi(z) from <r, A_S d> and ||A_S d||^2 in
-// O(|S|) per trial point; r and A_S^H r are formed afresh at each round start
-// and after a drop.
+// drop), so a Newton matrix costs O(|S|^2) lookups.  r = A_S z - b, A_S^H r and
+// phi are formed once for the seeded working set and then updated exactly: a
+// step z += t d by t A_S d, t G d and the change the line search measured (it
+// evaluates phi(z + t d) - phi(z) from <r, A_S d> and ||A_S d||^2 in O(|S|) per
+// trial point), a drop or an entry by the column's rank-one term.
 //
 // LDS holds the working set's columns A_S, the residual, the Gram and a packed
 // lower-triangular Hessian (for systems too large for the register solver);
@@ -624,12 +624,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         __syncthreads();
         gram_entries(a, sh, 0, s * (s + 1) / 2);
         fl += f8n * (unsigned long long)(s * (s + 1) / 2);
+        // r = A_S z - b, c = A_S^H r and phi are formed afresh for the seeded
+        // working set; afterwards every change updates them exactly: a step
+        // z += t d by r += t A_S d, c += t G d and the change the line search
+        // measured, a drop or an entry by the column's rank-one term.
+        bool fresh = true;
+        double ph = 0.0;
         for (int round = 0; round < a.rounds; ++round) {
-            // r = A_S z - b, c = A_S^H r and phi are formed afresh at the start of a
-            // round and after a drop; a step z += t d updates them exactly as
-            // r += t A_S d, c += t G d, phi += the change the line search measured.
-            bool fresh = true;
-            double ph = 0.0;
             for (int it = 0; it < 50 && s > 0; ++it) {
                 const int m2 = 2 * s;
                 if (fresh) {
@@ -716,9 +717,26 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                     }
                 }
                 if (drop >= 0) {
+                    // z_drop -> 0: r -= a z_drop, c_t -= G[t][drop] z_drop and
+                    // phi changes by -2 Re(conj(z_drop) c_drop) + G[drop][drop] |z_drop|^2 - lambda |z_drop|
+                    const double2 zd = sh.z[drop], cd = sh.c[drop], gdd = sh.Gc[tri(drop, drop)];
+                    const double azd = sqrt(zd.x * zd.x + zd.y * zd.y);
+                    ph += -2.0 * (zd.x * cd.x + zd.y * cd.y) + gdd.x * azd * azd - lam * azd;
+                    for (int nn = lane; nn < a.n; nn += 64) {
+                        const double2 av = ASat(sh, nn, drop);
+                        sh.r[nn] = make_double2(sh.r[nn].x - (av.x * zd.x - av.y * zd.y),
+                                                sh.r[nn].y - (av.x * zd.y + av.y * zd.x));
+                    }
+                    double2 cnew = make_double2(0.0, 0.0);
+                    if (lane < s) {
+                        const double2 g = gram_at(sh, lane, drop), cv = sh.c[lane];
+                        cnew = make_double2(cv.x - (g.x * zd.x - g.y * zd.y), cv.y - (g.x * zd.y + g.y * zd.x));
+                    }
+                    __syncthreads();
                     // remove column `drop` from the working set (lanes over rows of A_S)
                     for (int nn = lane; nn < a.n; nn += 64)
                         for (int t = drop; t + 1 < s; ++t) sh.AS[nn * kMaxSupp + t] = sh.AS[nn * kMaxSupp + t + 1];
+                    if (lane < s && lane != drop) sh.c[lane > drop ? lane - 1 : lane] = cnew;
                     if (lane == 0) {
                         for (int t = drop; t + 1 < s; ++t) {
                             sh.S[t] = sh.S[t + 1];
@@ -727,7 +745,6 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                     }
                     gram_drop(sh, s, drop);
                     --s;
-                    fresh = true;
                     continue;
                 }
                 const double slope = wsum(lane < m2 ? sh.grd[lane] * dv : 0.0);
@@ -801,7 +818,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             // the working set as the current point; its residual
             for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = (int8_t)t;
             __syncthreads();
-            if (fresh) phi_support(a, sh, b0, b1, sh.z, s, lam);
+            if (fresh) phi_support(a, sh, b0, b1, sh.z, s, lam);  // r only: c is formed afresh next round
             double F, kk;
             int vidx;
             full_pass<false>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
@@ -836,15 +853,36 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             // argmin_z |a z + r|^2 + lambda |z| = -S_{lambda/2}(a^H r) / ||a||^2
             const double mag = sqrt(gr * gr + gi * gi), tau = 0.5 * lam;
             const double sc = mag > tau ? (1.0 - tau / mag) / cn : 0.0;
+            const double2 zn = make_double2(-gr * sc, -gi * sc);
             if (lane == 0) {
                 sh.S[s] = vidx;
-                sh.z[s] = make_double2(-gr * sc, -gi * sc);
+                sh.z[s] = zn;
             }
             __syncthreads();
             if (sc == 0.0) break;
             ++s;
             gram_entries(a, sh, (s - 1) * s / 2, s * (s + 1) / 2);  // the new row of G
             fl += f8n * (unsigned long long)s;
+            if (!fresh) {
+                // the entry's rank-one term: r += a z_new, c_t += G[t][new] z_new,
+                // c_new = a^H r + ||a||^2 z_new, phi += 2 Re(conj(z_new) a^H r) + ||a||^2 |z_new|^2 + lambda |z_new|
+                const int tn = s - 1;
+                const double azn = sqrt(zn.x * zn.x + zn.y * zn.y);
+                ph += 2.0 * (zn.x * gr + zn.y * gi) + cn * azn * azn + lam * azn;
+                for (int nn = lane; nn < a.n; nn += 64) {
+                    const double2 av = ASat(sh, nn, tn);
+                    sh.r[nn] = make_double2(sh.r[nn].x + (av.x * zn.x - av.y * zn.y),
+                                            sh.r[nn].y + (av.x * zn.y + av.y * zn.x));
+                }
+                if (lane < tn) {
+                    const double2 g = gram_at(sh, lane, tn), cv = sh.c[lane];
+                    sh.c[lane] = make_double2(cv.x + (g.x * zn.x - g.y * zn.y), cv.y + (g.x * zn.y + g.y * zn.x));
+                } else if (lane == tn) {
+                    sh.c[lane] = make_double2(gr + cn * zn.x, gi + cn * zn.y);
+                }
+                __syncthreads();
+                fl += f8n + 8ull * (unsigned long long)s;
+            }
         }
         if (lane == 0) a.status[p] |= L1LS_PX_POLISHED;
         __syncthreads();
