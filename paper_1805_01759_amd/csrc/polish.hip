@@ -36,6 +36,7 @@
 // twelve pixels are in flight per CU.  Pixels are taken from a shared counter.
 #include "l1ls_internal.h"
 #include "wave_reduce.h"
+#include <type_traits>
 
 namespace l1ls {
 
@@ -59,6 +60,7 @@ __device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 struct PolishShared {
     double2 *r;         // n: residual A x - b (dynamic LDS)
     double2 *w;         // n: A_S d of the current Newton direction (dynamic LDS)
+    float2 *r32;        // n: the residual rounded to FP32 for the full pass (dynamic LDS)
     float2 *AS;         // n x kMaxSupp: columns of the working set (dynamic LDS)
     int16_t *nzl;       // l_pad: nonzero bins of the starting point (dynamic LDS)
     int8_t *sidx;       // l_pad: slot of bin m in the working set, or -1 (dynamic LDS)
@@ -144,20 +146,31 @@ __device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, float2 b
     return out;
 }
 
-// Full FP64 pass at the current point (sh.r its residual): natural KKT
-// residual, objective, and the worst off-support violator of |g| <= lambda.
+// Full pass at the current point (sh.r its residual): natural KKT residual,
+// objective, and the worst off-support violator of |g| <= lambda.
 // START: the point is the starting iterate x0 (its nonzero bins listed
 // in sh.nzl[0..nnz)); else it is z on the working set (sh.sidx, s entries).
+// The objective, the point and the KKT formula are FP64; the gradient
+// g = 2 A^H r is accumulated in FP64, or with F32 in FP32 from the residual
+// rounded once: its error, about 1e-7 of lambda, is far below the round-end
+// target tol/10 it is tested against (not below mode 2's); the check of the
+// starting point against tol itself stays FP64.
 // Magnitudes are compared squared; the prox scale (a square root and a
 // division) is formed only on lanes whose |v| passes the threshold.
-template <bool START>
+template <bool START, bool F32>
 __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2 *x0, int s, int nnz,
                           double lam, double lf, double inv_lf, double &F, double &kk, int &vidx)
 {
+    using acc_t = typename std::conditional<F32, float, double>::type;
     const int lane = threadIdx.x;
     double acc = 0.0, l1 = 0.0, km = 0.0, vbest = 0.0;
     vidx = -1;
-    for (int nn = lane; nn < a.n; nn += 64) acc += sh.r[nn].x * sh.r[nn].x + sh.r[nn].y * sh.r[nn].y;
+    for (int nn = lane; nn < a.n; nn += 64) {
+        const double2 rv = sh.r[nn];
+        acc += rv.x * rv.x + rv.y * rv.y;
+        if (F32) sh.r32[nn] = make_float2((float)rv.x, (float)rv.y);
+    }
+    if (F32) __syncthreads();
     if (START) {
         for (int q = lane; q < nnz; q += 64) {
             const float2 v = x0[sh.nzl[q]];
@@ -178,7 +191,11 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2
             const int m = lane + 64 * (c0 + k);
             mk[k] = m < a.l ? m : 0;  // a column in range; its result is discarded
         }
-        double gr[2] = {}, gi[2] = {};
+        acc_t gr[2] = {}, gi[2] = {};
+        auto rrow = [&](int n_) {
+            if constexpr (F32) return sh.r32[n_];
+            else return sh.r[n_];
+        };
         int nn = 0;
         for (; nn + 8 <= a.n; nn += 8) {
             float2 af[2][8];
@@ -188,21 +205,21 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2
                 for (int k = 0; k < 2; ++k) af[k][u] = a.A[(unsigned)((nn + u) * a.l_pad + mk[k])];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const double2 rv = sh.r[nn + u];
+                const auto rv = rrow(nn + u);
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    gr[k] += af[k][u].x * rv.x + af[k][u].y * rv.y;
-                    gi[k] += af[k][u].x * rv.y - af[k][u].y * rv.x;
+                    gr[k] += (acc_t)af[k][u].x * rv.x + (acc_t)af[k][u].y * rv.y;
+                    gi[k] += (acc_t)af[k][u].x * rv.y - (acc_t)af[k][u].y * rv.x;
                 }
             }
         }
         for (; nn < a.n; ++nn) {
-            const double2 rv = sh.r[nn];
+            const auto rv = rrow(nn);
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const float2 af = a.A[(unsigned)(nn * a.l_pad + mk[k])];
-                gr[k] += af.x * rv.x + af.y * rv.y;
-                gi[k] += af.x * rv.y - af.y * rv.x;
+                gr[k] += (acc_t)af.x * rv.x + (acc_t)af.y * rv.y;
+                gi[k] += (acc_t)af.x * rv.y - (acc_t)af.y * rv.x;
             }
         }
 #pragma unroll
@@ -477,6 +494,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         p += (size_t)a.n * sizeof(double2);
         sh.w = reinterpret_cast<double2 *>(p);
         p += (size_t)a.n * sizeof(double2);
+        sh.r32 = reinterpret_cast<float2 *>(p);
+        p += (size_t)a.n * sizeof(float2);
         sh.AS = reinterpret_cast<float2 *>(p);
         p += (size_t)a.n * kMaxSupp * sizeof(float2);
         sh.nzl = reinterpret_cast<int16_t *>(p);
@@ -527,7 +546,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         } else {
             double kk0;
             int vdummy;
-            full_pass<true>(a, sh, xo, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
+            // FP64 throughout: this decides "already solved" against tol itself
+            full_pass<true, false>(a, sh, xo, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
             fl += f8n * (unsigned long long)a.l;
             __syncthreads();
             if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
@@ -821,7 +841,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             if (fresh) phi_support(a, sh, b0, b1, sh.z, s, lam);  // r only: c is formed afresh next round
             double F, kk;
             int vidx;
-            full_pass<false>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
+            if (a.mode == 1)
+                full_pass<false, true>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
+            else
+                full_pass<false, false>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
             fl += f8n * (unsigned long long)(s + a.l);
             if (F <= fbest) {
                 fbest = F;
@@ -892,7 +915,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
 
 size_t polish_lds_bytes(int n, int l_pad)
 {
-    return (size_t)2 * n * sizeof(double2) + (size_t)l_pad * (sizeof(int16_t) + sizeof(int8_t)) +
+    return (size_t)2 * n * sizeof(double2) + (size_t)n * sizeof(float2) +
+           (size_t)l_pad * (sizeof(int16_t) + sizeof(int8_t)) +
            (size_t)n * kMaxSupp * sizeof(float2);
 }
 
