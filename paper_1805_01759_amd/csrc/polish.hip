@@ -30,10 +30,12 @@
 //
 // LDS holds the working set's columns A_S, the residual, the Gram and a packed
 // lower-triangular Hessian (for systems too large for the register solver);
-// the point with the least objective so far lives in X itself, and the dense
-// iterate is never materialised (a per-bin index into the working set stands
-// in for it), which keeps the footprint near 12.5 KB at N=25, L=256 so that
-// twelve pixels are in flight per CU.  Pixels are taken from a shared counter.
+// the starting point stays in X, the point with the least objective so far is
+// kept as its working set and values and written to X once at the end, and the
+// dense iterate is never materialised (a per-bin index into the working set
+// stands in for it), which keeps the footprint near 13 KB at N=25, L=256 so
+// that twelve pixels are in flight per CU.  Pixels are taken from a shared
+// counter.
 #include "l1ls_internal.h"
 #include "wave_reduce.h"
 #include <type_traits>
@@ -71,6 +73,9 @@ struct PolishShared {
     double grd[kMaxM], dir[kMaxM], invd[kMaxM];
     int S[kMaxSupp];
     int cnt;
+    double2 zb[kMaxSupp];  // the point with the least objective so far, on slots Sb[0..sb)
+    int Sb[kMaxSupp];
+    int sb;                // -1: the starting point (already in X) is the best
 };
 
 __device__ __forceinline__ double2 Aat(const PolishArgsDev &a, int n, int m)
@@ -527,6 +532,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         const float2 b1 = lane + 64 < a.n ? b[lane + 64] : make_float2(0.0f, 0.0f);
         float2 *xo = a.X + (size_t)p * a.l;
         for (int m = lane; m < a.l_pad; m += 64) sh.sidx[m] = -1;
+        if (lane == 0) sh.sb = -1;
         __syncthreads();
         // objective and FP64 natural KKT residual of the starting point (the
         // point with the least objective so far is kept in X itself)
@@ -848,10 +854,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             fl += f8n * (unsigned long long)(s + a.l);
             if (F <= fbest) {
                 fbest = F;
-                for (int m = lane; m < a.l; m += 64) {
-                    const int t = sh.sidx[m];
-                    xo[m] = t >= 0 ? make_float2((float)sh.z[t].x, (float)sh.z[t].y) : make_float2(0.0f, 0.0f);
+                if (lane < s) {
+                    sh.Sb[lane] = sh.S[lane];
+                    sh.zb[lane] = sh.z[lane];
                 }
+                if (lane == 0) sh.sb = s;
             }
             __syncthreads();
             for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = -1;
@@ -906,6 +913,18 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                 __syncthreads();
                 fl += f8n + 8ull * (unsigned long long)s;
             }
+        }
+        // write the best point (complex64) unless it is the starting one
+        if (sh.sb >= 0) {
+            const int sb = sh.sb;
+            for (int t = lane; t < sb; t += 64) sh.sidx[sh.Sb[t]] = (int8_t)t;
+            __syncthreads();
+            for (int m = lane; m < a.l; m += 64) {
+                const int t = sh.sidx[m];
+                xo[m] = t >= 0 ? make_float2((float)sh.zb[t].x, (float)sh.zb[t].y) : make_float2(0.0f, 0.0f);
+            }
+            __syncthreads();
+            for (int t = lane; t < sb; t += 64) sh.sidx[sh.Sb[t]] = -1;
         }
         if (lane == 0) a.status[p] |= L1LS_PX_POLISHED;
         __syncthreads();
