@@ -453,9 +453,10 @@ __device__ bool newton_regs(PolishShared &sh, int m2, double mu, double &d)
     for (int j = 0; j < NS; ++j) {
         const double piv = lane_value(row[j], j);
         if (!(piv > 0.0)) return false;
-        // 1/sqrt(piv): hardware estimate refined by two Newton-Raphson steps
+        // 1/sqrt(piv): hardware estimate refined by one Newton-Raphson step (the
+        // factor only shapes the Newton direction; its accuracy squares to about
+        // 1e-13, below what the stopping rules resolve)
         double iv = __builtin_amdgcn_rsq(piv);
-        iv = iv * fma(-0.5 * piv, iv * iv, 1.5);
         iv = iv * fma(-0.5 * piv, iv * iv, 1.5);
         if (lane == j) invl = iv;
         const double lj = row[j] * iv;  // lane i >= j: L_ij
