@@ -428,10 +428,9 @@ __device__ double newton_dir(const PolishShared &sh, int m2)
 
 // The Newton system (H + mu I) d = -grd of order m2 <= NS solved in registers:
 // lane i < NS holds row i of H (the identity pads rows and columns m2..NS-1),
-// a right-looking Cholesky broadcasts each column with readlane and keeps the
-// unit-diagonal factor U (L = U diag(L_jj)), so that both substitutions need one
-// broadcast per column and no selects; U is transposed once through LDS for
-// the backward substitution.
+// a right-looking U D U^T factorisation broadcasts each column with readlane,
+// so that both substitutions need one broadcast per column and no selects; U
+// is transposed once through LDS for the backward substitution.
 // Returns false (wave-uniform) if H is not positive definite; lane i ends
 // holding d_i.
 template <int NS>
@@ -446,31 +445,31 @@ __device__ bool newton_regs(PolishShared &sh, int m2, double mu, double &d)
         else
             row[k] = k == lane ? 1.0 : 0.0;
     }
-    // H = L L^T with L = U D, U unit lower, D = diag(L_jj): lane i keeps U_ij in
-    // row[j] below the diagonal (0 on and above it) and 1/L_ii in invl.
-    double invl = 0.0;
+    // H = U D U^T, U unit lower, D diagonal (a square-root-free Cholesky): lane i
+    // keeps U_ij in row[j] below the diagonal (0 on and above it) and 1/D_ii in
+    // dinv.  Column j is eliminated with its unscaled entries c_kj = D_j U_kj,
+    // whose broadcasts do not wait for the reciprocal of the pivot.
+    double dinv = 0.0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         const double piv = lane_value(row[j], j);
         if (!(piv > 0.0)) return false;
-        // 1/sqrt(piv): hardware estimate refined by one Newton-Raphson step (the
-        // factor only shapes the Newton direction; its accuracy squares to about
-        // 1e-13, below what the stopping rules resolve)
-        double iv = __builtin_amdgcn_rsq(piv);
-        iv = iv * fma(-0.5 * piv, iv * iv, 1.5);
-        if (lane == j) invl = iv;
-        const double lj = row[j] * iv;  // lane i >= j: L_ij
-        const double act = lane > j ? lj : 0.0;
+        // 1/piv: hardware estimate refined by one Newton-Raphson step
+        double rp = __builtin_amdgcn_rcp(piv);
+        rp = fma(rp, fma(-piv, rp, 1.0), rp);
+        if (lane == j) dinv = rp;
+        const double cj = row[j];                 // lane i >= j: c_ij
+        const double uj = lane > j ? cj * rp : 0.0;  // U_ij
 #pragma unroll
-        for (int k = j + 1; k < NS; ++k) row[k] -= act * lane_value(lj, k);  // - L_ij L_kj
-        row[j] = act * iv;  // U_ij
+        for (int k = j + 1; k < NS; ++k) row[k] -= uj * lane_value(cj, k);  // - U_ij c_kj
+        row[j] = uj;
     }
-    // U y' = -grd (unit diagonal: y'_j is final when its column is reached)
+    // U y = -grd (unit diagonal: y_j is final when its column is reached)
     double v = lane < m2 ? -sh.grd[lane] : 0.0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) v -= row[j] * lane_value(v, j);
-    // L y = -grd is y = D^-1 y', and L^T d = y is U^T d = D^-2 y'
-    v *= invl * invl;
+    // D w = y on each lane
+    v *= dinv;
     // U^T d = w: U_ji (i < j) is lane j's row[i]; the factor is transposed through
     // LDS (past the packed Hessian, which a retry with a shift still needs) so
     // that lane i holds column i of U
