@@ -515,20 +515,34 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
             }
             if (h == 0) sPS[w * 16 + j] = f4{d2, s1, kmax, 0.0f};
             __syncthreads();
-#pragma unroll
-            for (int t = 0; t < T; ++t) Wr[t] = Wi[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            f4 S = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            for (int ww = 0; ww < W; ++ww) {
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    Wr[t] += sPW[((size_t)ww * 2 * T + 2 * t) * 64 + lane];
-                    Wi[t] += sPW[((size_t)ww * 2 * T + 2 * t + 1) * 64 + lane];
+            // two stages: each thread sums one entry over the waves (in wave order,
+            // into wave 0's slot), then every wave reads the sums
+            {
+                const int EW = 2 * T * 64, E = EW + 16;
+                for (int e = tid; e < E; e += blockDim.x) {
+                    if (e < EW) {
+                        f4 acc = sPW[e];
+                        for (int ww = 1; ww < W; ++ww) acc += sPW[(size_t)ww * EW + e];
+                        sPW[e] = acc;
+                    } else {
+                        f4 acc = sPS[e - EW];
+                        for (int ww = 1; ww < W; ++ww) {
+                            const f4 ps = sPS[ww * 16 + e - EW];
+                            acc[0] += ps[0];
+                            acc[1] += ps[1];
+                            acc[2] = fmaxf(acc[2], ps[2]);
+                        }
+                        sPS[e - EW] = acc;
+                    }
                 }
-                const f4 ps = sPS[ww * 16 + j];
-                S[0] += ps[0];
-                S[1] += ps[1];
-                S[2] = fmaxf(S[2], ps[2]);
             }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                Wr[t] = sPW[(size_t)(2 * t) * 64 + lane];
+                Wi[t] = sPW[(size_t)(2 * t + 1) * 64 + lane];
+            }
+            const f4 S = sPS[j];
             __syncthreads();
             float w2 = 0.0f;
 #pragma unroll
