@@ -245,14 +245,17 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
     // G needs no reset (the next adjoint overwrites it); everything that enters
     // an extrapolation, even with beta = 0, is cleared so that nothing non-finite
     // of the previous pixel survives.
-    auto refill = [&](uint32_t mask) {
+    // `got`: thread 0's result of the queue atomic for this mask, issued as soon as
+    // the retiring slots are known so that its latency hides under the acceptance
+    // (the barrier that publishes it is the only one here: the next write of sQ
+    // comes after the next trial's barriers).
+    auto refill = [&](uint32_t mask, uint32_t got) {
         if (mask == 0) return;
         const bool mine = (mask >> j) & 1u;
         bool fresh = false;
         if (!qdone) {
             const uint32_t nfree = __popc(mask);
-            __syncthreads();
-            if (tid == 0) sQ[0] = atomicAdd(a.queue, nfree);
+            if (tid == 0) sQ[0] = got;
             __syncthreads();
             const uint64_t base = sQ[0];
             if (base + nfree >= (uint64_t)a.p) qdone = true;
@@ -376,7 +379,8 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
     };
 
     unsigned long long n_fwd = 0, n_adj = 0;  // pixel products (thread 0 counts)
-    refill(0xFFFFu);
+    uint32_t qgot = 0;                        // thread 0: queue position for the retiring slots
+    refill(0xFFFFu, tid == 0 ? atomicAdd(a.queue, 16u) : 0u);
     if (__ballot(active) == 0) return;
     adjoint();
     n_adj += __popcll(__ballot(active && h == 0));
@@ -556,6 +560,10 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
                 conv = kkt <= a.tol;
                 const bool capped = (k - 1) >= a.fista_cap;
                 retire = active && (bad || nonfinite || conv || capped);
+                {
+                    const uint32_t rm = (uint32_t)(__ballot(retire && h == 0) & 0xFFFFull);
+                    if (tid == 0 && rm != 0u && !qdone) qgot = atomicAdd(a.queue, (uint32_t)__popc(rm));
+                }
                 if (retire && w == 0 && h == 0) {
                     uint32_t st = 0;
                     if (bad) st |= L1LS_PX_BAD_LAMBDA;
@@ -676,7 +684,7 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
         // ---- refill retired slots, stop when the tile is empty
         const uint32_t rmask = (uint32_t)(__ballot(retire && h == 0) & 0xFFFFull);
         if (retire) active = false;
-        refill(rmask);
+        refill(rmask, qgot);
         if (__ballot(active) == 0) break;
         adjoint();
         n_adj += __popcll(__ballot(active && h == 0));
