@@ -41,6 +41,7 @@ KERNEL_SOURCES = {
     "certify_kernel": ("certify.hip", "wave_reduce.h"),
 }
 PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
+POLISH_AFTER = 12          # FP32 iterations before a pixel goes to the FP64 stage
 
 
 def kernel_sha(kernel: str) -> str:
@@ -221,7 +222,7 @@ def main():
     ap.add_argument("--workload", default="scene", choices=sorted(WORKLOADS) + ["unrolled", "batched"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
     ap.add_argument("--max-iter", type=int, default=500)
-    ap.add_argument("--polish-after", type=int, default=12)
+    ap.add_argument("--polish-after", type=int, default=POLISH_AFTER)
     ap.add_argument("--polish", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
