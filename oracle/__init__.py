@@ -85,6 +85,16 @@ def lib():
         L.orc_exact_batch.restype = None
         L.orc_unrolled_batch.argtypes = [I, I, I64, P, P, D, D, I, I, P]
         L.orc_unrolled_batch.restype = None
+        L.orc_block_lipschitz.argtypes = [I, I, P, I, I]
+        L.orc_block_lipschitz.restype = D
+        L.orc_block_pick.argtypes = [I, P, D]
+        L.orc_block_pick.restype = I
+        L.orc_rbpg_blocks.argtypes = [I, I, P, P, D, D, I, P, P, ctypes.POINTER(RbpgOpts), P,
+                                      ctypes.POINTER(RbpgInfo)]
+        L.orc_rbpg_blocks.restype = None
+        L.orc_rbpg_blocks_batch.argtypes = [I, I, I64, P, P, P, I64, I, P, ctypes.POINTER(RbpgOpts),
+                                            I, P, P, P, P]
+        L.orc_rbpg_blocks_batch.restype = None
         L.orc_default_threads.argtypes = []
         L.orc_default_threads.restype = I
         _lib = L
@@ -183,6 +193,56 @@ def rbpg_batch(A, B, lam, *, tol=1e-4, max_iter=500, c_alpha=0.5, alpha0=0.0,
     o = RbpgOpts(alpha0, c_alpha, tol, max_iter, int(backtracking), int(monotone))
     lib().orc_rbpg_batch(n, l, p, _ptr(A), _ptr(B), _ptr(lam), stride, ctypes.byref(o),
                          int(nthreads), _ptr(X), _ptr(iters), _ptr(kkt), _ptr(conv))
+    return X, {"iters": iters, "kkt_nat": kkt, "converged": conv.astype(bool)}
+
+
+def block_lipschitz(A, J: int):
+    """L_j = 2 lambda_max(A_j A_j^H) of the J contiguous column blocks (Eq. (14))."""
+    A = _c128(A)
+    n, l = A.shape
+    return np.array([lib().orc_block_lipschitz(n, l, _ptr(A), int(J), j) for j in range(J)])
+
+
+def block_pick(Lb, u: float) -> int:
+    """The block that the uniform draw u selects with P_j = L_j / sum L (Eq. (14))."""
+    Lb = np.ascontiguousarray(Lb, dtype=np.float64)
+    return int(lib().orc_block_pick(Lb.size, _ptr(Lb), float(u)))
+
+
+def rbpg_blocks(A, b, lam, J: int, u, *, tol=1e-4, max_iter=500, c_alpha=0.5, alpha0=0.0,
+                backtracking=True, monotone=True, Lf=None):
+    """Algorithm 1 with J blocks on one pixel; u[k-1] is the draw of iteration k."""
+    A, b = _c128(A), _c128(b)
+    n, l = A.shape
+    Lf = lipschitz(A) if Lf is None else Lf
+    Lb = block_lipschitz(A, J)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert u.size >= max_iter
+    x = np.zeros(l, np.complex128)
+    o = RbpgOpts(alpha0, c_alpha, tol, max_iter, int(backtracking), int(monotone))
+    info = RbpgInfo()
+    lib().orc_rbpg_blocks(n, l, _ptr(A), _ptr(b), float(lam), float(Lf), int(J), _ptr(Lb), _ptr(u),
+                          ctypes.byref(o), _ptr(x), ctypes.byref(info))
+    return x, {f: getattr(info, f) for f, _ in RbpgInfo._fields_}
+
+
+def rbpg_blocks_batch(A, B, lam, J: int, u, *, tol=1e-4, max_iter=500, c_alpha=0.5, alpha0=0.0,
+                      backtracking=True, monotone=True, nthreads=0):
+    """Algorithm 1 with J blocks on every pixel row of B (the draws u are shared)."""
+    A, B = _c128(A), _c128(B)
+    n, l = A.shape
+    p = B.shape[0]
+    lam, stride = _lam_array(lam, p)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert u.size >= max_iter
+    X = np.zeros((p, l), np.complex128)
+    iters = np.zeros(p, np.int32)
+    kkt = np.zeros(p, np.float64)
+    conv = np.zeros(p, np.int32)
+    o = RbpgOpts(alpha0, c_alpha, tol, max_iter, int(backtracking), int(monotone))
+    lib().orc_rbpg_blocks_batch(n, l, p, _ptr(A), _ptr(B), _ptr(lam), stride, int(J), _ptr(u),
+                                ctypes.byref(o), int(nthreads), _ptr(X), _ptr(iters), _ptr(kkt),
+                                _ptr(conv))
     return X, {"iters": iters, "kkt_nat": kkt, "converged": conv.astype(bool)}
 
 

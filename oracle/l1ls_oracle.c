@@ -11,6 +11,8 @@
  *   Eq. (14)      L = ||A^T A|| (block Lipschitz; J = 1 -> whole A) -> orc_lipschitz
  *   Eq. (15)      backtracking condition      -> orc_rbpg
  *   Algorithm 1   RBPG with backtracking, J=1 -> orc_rbpg
+ *   Eqs. (13)-(14), Algorithm 1 with J blocks  -> orc_rbpg_blocks, orc_block_lipschitz,
+ *                                                orc_block_pick
  */
 #define _GNU_SOURCE
 #include "l1ls_oracle.h"
@@ -276,6 +278,138 @@ void orc_rbpg(int n, int l, const ocplx *A, const ocplx *b, double lambda, doubl
     free(rb);
 }
 
+
+/* ------------------------------- Algorithm 1 with J blocks, Eqs. (13)-(14) */
+
+/* Block j of J covers bins [j w, min(l, (j+1) w)), w = ceil(l / J). */
+static void block_range(int l, int J, int j, int *m0, int *m1)
+{
+    const int w = (l + J - 1) / J;
+    *m0 = j * w < l ? j * w : l;
+    *m1 = (j + 1) * w < l ? (j + 1) * w : l;
+}
+
+double orc_block_lipschitz(int n, int l, const ocplx *A, int J, int j)
+{
+    int m0, m1;
+    block_range(l, J, j, &m0, &m1);
+    const int lb = m1 - m0;
+    if (lb <= 0) return 0.0;
+    ocplx *Aj = malloc(sizeof(ocplx) * (size_t)n * lb);
+    for (int i = 0; i < n; ++i)
+        for (int m = 0; m < lb; ++m) Aj[(int64_t)i * lb + m] = A[(int64_t)i * l + m0 + m];
+    const double L = orc_lipschitz(n, lb, Aj);  /* 2 lambda_max(A_j A_j^H) */
+    free(Aj);
+    return L;
+}
+
+int orc_block_pick(int J, const double *Lb, double u)
+{
+    double tot = 0;
+    for (int j = 0; j < J; ++j) tot += Lb[j];
+    double acc = 0;
+    for (int j = 0; j < J; ++j) {
+        acc += Lb[j];
+        if (u * tot < acc) return j;
+    }
+    return J - 1;
+}
+
+void orc_rbpg_blocks(int n, int l, const ocplx *A, const ocplx *b, double lambda, double Lf,
+                     int J, const double *Lb, const double *u, const orc_rbpg_opts *opt,
+                     ocplx *x, orc_rbpg_info *info)
+{
+    ocplx *xprev = calloc(l, sizeof(ocplx)), *y = malloc(sizeof(ocplx) * l);
+    ocplx *g = malloc(sizeof(ocplx) * l), *xb = malloc(sizeof(ocplx) * l);
+    ocplx *ry = malloc(sizeof(ocplx) * n), *rb = malloc(sizeof(ocplx) * n);
+    double *alpha = malloc(sizeof(double) * J), *afloor = malloc(sizeof(double) * J);
+    int *cnt = calloc(J, sizeof(int));
+    for (int jb = 0; jb < J; ++jb) {
+        int m0, m1;
+        block_range(l, J, jb, &m0, &m1);
+        double colmax = 0;
+        for (int m = m0; m < m1; ++m) {
+            double c = 0;
+            for (int i = 0; i < n; ++i) c += cabs2(A[(int64_t)i * l + m]);
+            colmax = fmax(colmax, c);
+        }
+        alpha[jb] = opt->alpha0 > 0 ? opt->alpha0 : (colmax > 0 ? 1.0 / (2.0 * colmax) : 1.0);
+        afloor[jb] = Lb[jb] > 0 ? 1.0 / Lb[jb] : alpha[jb];
+        if (opt->backtracking && alpha[jb] < afloor[jb]) alpha[jb] = afloor[jb];
+    }
+
+    memset(x, 0, sizeof(ocplx) * l); /* Init: x^(0) = y^(0) = 0 */
+    double Fx = sqnorm(n, b);
+    int k = 0, backtracks = 0;
+    double kkt = orc_kkt_nat(n, l, A, b, lambda, Lf, x);
+    int done = kkt <= opt->tol;
+
+    for (k = 1; k <= opt->max_iter && !done; ++k) {
+        /* i_k drawn with P_i = L_i / sum_j L_j (Eq. (14)); u[k-1] is the draw */
+        const int ib = orc_block_pick(J, Lb, u[k - 1]);
+        int m0, m1;
+        block_range(l, J, ib, &m0, &m1);
+        /* Eqs. (11)-(12) on block i_k with its own update count and its own
+         * previous value; the other blocks of y are those of x^k */
+        ++cnt[ib];
+        const double beta = fmax(0.0, (double)(cnt[ib] - 2) / (double)(cnt[ib] + 1));
+        memcpy(y, x, sizeof(ocplx) * l);
+        for (int m = m0; m < m1; ++m) y[m] = x[m] + beta * (x[m] - xprev[m]);
+        residual(n, l, A, b, y, ry);
+        grad_from_residual(n, l, A, ry, g); /* only the block's part is used */
+        const double fy = sqnorm(n, ry);
+        double fb;
+        for (;;) {
+            /* Eq. (13): the block's prox-gradient step */
+            memcpy(xb, y, sizeof(ocplx) * l);
+            for (int m = m0; m < m1; ++m) xb[m] = prox1(y[m] - alpha[ib] * g[m], alpha[ib] * lambda);
+            residual(n, l, A, b, xb, rb);
+            fb = sqnorm(n, rb);
+            if (!opt->backtracking) break;
+            /* Eq. (15) on the block */
+            double lin = 0, d2 = 0;
+            for (int m = m0; m < m1; ++m) {
+                ocplx d = xb[m] - y[m];
+                lin += creal(conj(g[m]) * d);
+                d2 += cabs2(d);
+            }
+            if (fb <= fy + lin + d2 / (2.0 * alpha[ib])) break;
+            if (alpha[ib] <= afloor[ib]) break;
+            alpha[ib] = fmax(opt->c_alpha * alpha[ib], afloor[ib]);
+            ++backtracks;
+        }
+        const double Fb = fb + lambda * norm1(l, xb);
+        for (int m = m0; m < m1; ++m) xprev[m] = x[m];
+        if (!opt->monotone || Fb <= Fx) { /* monotone accept (ties accept) */
+            memcpy(x, xb, sizeof(ocplx) * l);
+            Fx = Fb;
+        }
+        /* the KKT test once per J block updates */
+        if (k % J == 0) {
+            kkt = orc_kkt_nat(n, l, A, b, lambda, Lf, x);
+            if (kkt <= opt->tol) done = 1;
+        }
+    }
+    if (info) {
+        info->iters = done ? k - 1 : opt->max_iter;
+        if (info->iters < 0) info->iters = 0;
+        info->backtracks = backtracks;
+        info->alpha = alpha[0];
+        info->kkt_nat = orc_kkt_nat(n, l, A, b, lambda, Lf, x);
+        info->objective = orc_objective(n, l, A, b, lambda, x);
+        info->converged = info->kkt_nat <= opt->tol;
+    }
+    free(xprev);
+    free(y);
+    free(g);
+    free(xb);
+    free(ry);
+    free(rb);
+    free(alpha);
+    free(afloor);
+    free(cnt);
+}
+
 /* ------------------------------------------ active-set Newton polish (FP64) */
 
 /* Cholesky solve of the SPD system H d = rhs (size m, H overwritten).
@@ -508,7 +642,7 @@ int orc_default_threads(void)
 }
 
 typedef struct {
-    int kind; /* 0 rbpg, 1 exact, 2 unrolled */
+    int kind; /* 0 rbpg, 1 exact, 2 unrolled, 3 rbpg with J blocks */
     int n, l;
     int64_t p0, p1;
     const ocplx *A, *B;
@@ -520,6 +654,8 @@ typedef struct {
     ocplx *X;
     int32_t *iters, *converged;
     double *kkt, *kkt_sub, *kkt_nat, *gap, *objective;
+    int J;
+    const double *Lb, *u;
 } job_t;
 
 static void unrolled_one(int n, int l, const ocplx *A, const ocplx *b, double lambda,
@@ -553,7 +689,13 @@ static void *worker(void *arg)
             continue;
         }
         double lam = j->lambda[j->lambda_stride * p];
-        if (j->kind == 0) {
+        if (j->kind == 3) {
+            orc_rbpg_info info;
+            orc_rbpg_blocks(j->n, j->l, j->A, b, lam, j->Lf, j->J, j->Lb, j->u, j->opt, x, &info);
+            if (j->iters) j->iters[p] = info.iters;
+            if (j->kkt) j->kkt[p] = info.kkt_nat;
+            if (j->converged) j->converged[p] = info.converged;
+        } else if (j->kind == 0) {
             orc_rbpg_info info;
             orc_rbpg(j->n, j->l, j->A, b, lam, j->Lf, j->opt, x, &info);
             if (j->iters) j->iters[p] = info.iters;
@@ -614,6 +756,24 @@ void orc_rbpg_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,
     j.opt = opt; j.Lf = orc_lipschitz(n, l, A); j.X = X;
     j.iters = iters; j.kkt = kkt; j.converged = converged;
     run_jobs(&j, p, nthreads);
+}
+
+void orc_rbpg_blocks_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,
+                           const double *lambda, int64_t lambda_stride, int J, const double *u,
+                           const orc_rbpg_opts *opt, int nthreads, ocplx *X, int32_t *iters,
+                           double *kkt, int32_t *converged)
+{
+    double *Lb = malloc(sizeof(double) * J);
+    for (int jb = 0; jb < J; ++jb) Lb[jb] = orc_block_lipschitz(n, l, A, J, jb);
+    job_t j;
+    memset(&j, 0, sizeof j);
+    j.kind = 3;
+    j.n = n; j.l = l; j.A = A; j.B = B; j.lambda = lambda; j.lambda_stride = lambda_stride;
+    j.opt = opt; j.Lf = orc_lipschitz(n, l, A); j.X = X;
+    j.iters = iters; j.kkt = kkt; j.converged = converged;
+    j.J = J; j.Lb = Lb; j.u = u;
+    run_jobs(&j, p, nthreads);
+    free(Lb);
 }
 
 void orc_exact_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,

@@ -92,6 +92,27 @@ int orc_polish(int n, int l, const ocplx *A, const ocplx *b, double lambda, doub
 /* Batched drivers, threads over pixels.  lambda has stride lambda_stride
  * (0 => one scalar for all pixels).  Any diagnostic pointer may be NULL.
  * nthreads <= 0 selects the number of online cores. */
+/* Algorithm 1 with J blocks (Eqs. (13)-(14)).  Block j covers bins
+ * [j w, min(L, (j+1) w)), w = ceil(L/J); L_j = 2 lambda_max(A_j A_j^H) (the
+ * Lipschitz constant of the block gradient, Eq. (14)).  Iteration k updates the
+ * block i_k drawn with P_i = L_i / sum L (u[k-1] in [0,1) is the draw: i_k is the
+ * first j with u sum L < L_0 + ... + L_j).  Readings where the paper is silent:
+ * the extrapolation of Eqs. (11)-(12) uses the block's own update count c
+ * (beta = max(0, (c-2)/(c+1))) and the block's value before its last update;
+ * each block keeps its own step (start 1/(2 max_{l in j} ||a_l||^2), shrunk by
+ * C_alpha while Eq. (15) fails on the block, floored at 1/L_j); the monotone test
+ * compares F of x^k with block i_k replaced by x-bar; KKT_nat(x^k) <= tol is
+ * tested every J iterations.  J = 1 is orc_rbpg. */
+double orc_block_lipschitz(int n, int l, const ocplx *A, int J, int j);
+int orc_block_pick(int J, const double *Lb, double u);
+void orc_rbpg_blocks(int n, int l, const ocplx *A, const ocplx *b, double lambda, double Lf,
+                     int J, const double *Lb, const double *u, const orc_rbpg_opts *opt,
+                     ocplx *x, orc_rbpg_info *info);
+void orc_rbpg_blocks_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,
+                           const double *lambda, int64_t lambda_stride, int J, const double *u,
+                           const orc_rbpg_opts *opt, int nthreads, ocplx *X, int32_t *iters,
+                           double *kkt, int32_t *converged);
+
 void orc_rbpg_batch(int n, int l, int64_t p, const ocplx *A, const ocplx *B,
                     const double *lambda, int64_t lambda_stride,
                     const orc_rbpg_opts *opt, int nthreads, ocplx *X,
