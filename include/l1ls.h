@@ -121,6 +121,27 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
                        l1ls_c32 *X, const l1ls_diag *diag, void *workspace, size_t ws_bytes,
                        hipStream_t stream);
 
+/* Algorithm 1 with J column blocks (randomized block prox-gradient, Eqs. (13)-(14)).
+ * Bins are split into J contiguous blocks of ceil(l/J); iteration k of a pixel
+ * updates the block that draws[k-1] selects with P_i = L_i / sum_j L_j,
+ * L_i = 2 lambda_max(A_i A_i^H) (the first i with draws[k-1] sum L < L_0 + ... + L_i).
+ * Per block: its own update count for the extrapolation weight of Eqs. (11)-(12),
+ * its own step for Eq. (15) (start 1/(2 max ||a_l||^2) over its columns, floor
+ * 1/L_i), and the monotone test of Algorithm 1 on the objective with the block
+ * replaced; the KKT residual is tested every J iterations.  J = 1 is Algorithm 1
+ * with one block.  The FP64 refinement and certificate then run as in l1ls_solve
+ * (opt->precision is ignored: the block products are FP32).
+ *  blocks   J, 1 <= J <= min(64, l); n <= 64
+ *  draws    device double, at least min(max_iter, polish_after) values in [0, 1),
+ *           shared by all pixels (pixel-local iteration k uses draws[k-1])
+ *  other arguments as l1ls_solve (same workspace size); l1ls_solve_counters
+ *  out[0] then holds the iteration's FP32 flops (8 per complex multiply-add)
+ *  instead of a count of products, and out[1] is 0. */
+l1ls_status l1ls_solve_blocks(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                              const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                              int32_t blocks, const double *draws, l1ls_c32 *X, const l1ls_diag *diag,
+                              void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batched stacks of uneven size (each with its own A, N, L and pixel count) in
  * one persistent launch per shape class.  The plan holds host tables and the

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "L1LS_OK", -1: "L1LS_ERR_INVALID_ARG", -2: "L1LS_ERR_UNSUPPOR
                 -3: "L1LS_ERR_WORKSPACE", -4: "L1LS_ERR_HIP", -5: "L1LS_ERR_INTERNAL"}
 
 EXPORTS = [
-    "l1ls_options_default", "l1ls_workspace_size", "l1ls_solve",
+    "l1ls_options_default", "l1ls_workspace_size", "l1ls_solve", "l1ls_solve_blocks",
     "l1ls_plan_create", "l1ls_plan_workspace_size", "l1ls_plan_execute", "l1ls_plan_destroy",
     "l1ls_plan_describe",
     "l1ls_unrolled_tape_size", "l1ls_unrolled_backward_ws_size", "l1ls_unrolled_forward",
@@ -75,6 +75,9 @@ def load() -> ctypes.CDLL:
     L.l1ls_solve.argtypes = [I32, I32, I64, P, P, P, I64, ctypes.POINTER(Options), P,
                              ctypes.POINTER(Diag), P, SZ, P]
     L.l1ls_solve.restype = st
+    L.l1ls_solve_blocks.argtypes = [I32, I32, I64, P, P, P, I64, ctypes.POINTER(Options), I32, P, P,
+                                    ctypes.POINTER(Diag), P, ctypes.c_size_t, P]
+    L.l1ls_solve_blocks.restype = st
     L.l1ls_plan_create.argtypes = [ctypes.POINTER(Stack), I32, ctypes.POINTER(Options),
                                    ctypes.POINTER(P)]
     L.l1ls_plan_create.restype = st

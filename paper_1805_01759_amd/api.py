@@ -85,11 +85,14 @@ def workspace_size(n: int, l: int, p: int, opts: _lib.Options | None = None) -> 
 
 
 def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = None,
-          workspace: Workspace | None = None, stream=None, **opts):
+          workspace: Workspace | None = None, stream=None, blocks: int = 0,
+          draws: torch.Tensor | None = None, **opts):
     """Solve min ||A x - b_p||^2 + lambda_p ||x||_1 for every row b_p of B.
 
     Returns (X, diag) with X (P, L) complex64 and diag a dict of device tensors
     (iters int32, kkt float32, objective float32, status int32 bits, nnz int32).
+    blocks > 0: Algorithm 1 with that many column blocks (l1ls_solve_blocks),
+    draws a float64 device tensor of uniform draws, one per iteration.
     """
     L = _lib.load()
     A, B, lam_t, stride = _check_inputs(A, B, lam)
@@ -107,9 +110,19 @@ def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = N
     d = _lib.Diag(diag["iters"].data_ptr(), diag["kkt"].data_ptr(), diag["objective"].data_ptr(),
                   diag["status"].data_ptr(), diag["nnz"].data_ptr())
     ws = (workspace or _default_ws).get(workspace_size(n, l, p, o), B.device)
-    _lib.check(L.l1ls_solve(n, l, p, _ptr(A), _ptr(B), _ptr(lam_t), stride, ctypes.byref(o),
-                            _ptr(X), ctypes.byref(d), _ptr(ws), ws.numel(), _stream(stream)),
-               "l1ls_solve")
+    if blocks:
+        if draws is None or draws.dtype != torch.float64 or not draws.is_cuda or not draws.is_contiguous():
+            raise TypeError("draws must be a contiguous float64 device tensor")
+        if draws.numel() < min(o.max_iter, o.polish_after if o.polish_after > 0 else o.max_iter):
+            raise ValueError("draws needs one value per iteration")
+        _lib.check(L.l1ls_solve_blocks(n, l, p, _ptr(A), _ptr(B), _ptr(lam_t), stride, ctypes.byref(o),
+                                       int(blocks), _ptr(draws), _ptr(X), ctypes.byref(d), _ptr(ws),
+                                       ws.numel(), _stream(stream)),
+                   "l1ls_solve_blocks")
+    else:
+        _lib.check(L.l1ls_solve(n, l, p, _ptr(A), _ptr(B), _ptr(lam_t), stride, ctypes.byref(o),
+                                _ptr(X), ctypes.byref(d), _ptr(ws), ws.numel(), _stream(stream)),
+                   "l1ls_solve")
     diag["_ws"] = ws
     return X, diag
 

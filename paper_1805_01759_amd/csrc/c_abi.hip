@@ -61,6 +61,8 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     off = align_up(off + (size_t)p * sizeof(float), 256);
     w.polish_list = off;
     off = align_up(off + (size_t)p * sizeof(int32_t), 256);
+    w.blocks = off;
+    off = align_up(off + (size_t)kMaxBlocks * sizeof(BlockConsts), 256);
     w.total = off;
     return w;
 }
@@ -139,7 +141,7 @@ struct TimedLaunch {
 l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
                         const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
                         l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
-                        hipStream_t s, int choice)
+                        hipStream_t s, int choice, int blocks, const double *draws)
 {
     l1ls_status st = check_shape(n, l, p);
     if (st != L1LS_OK) return st;
@@ -199,10 +201,20 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     fa.backtracking = opt->backtracking ? 1 : 0;
     fa.monotone = opt->monotone ? 1 : 0;
     fa.polish = opt->fp64_polish;
-    if (choice == kAuto) choice = mfma_supports(n, l) ? kMfma : kWave;
-    if (choice == kMfma && !mfma_supports(n, l))
-        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
-    {
+    if (choice == kBlocks) {
+        BlocksArgs ba;
+        ba.f = fa;
+        ba.J = blocks;
+        ba.u = draws;
+        ba.bc = (const BlockConsts *)(w + lay.blocks);
+        e = launch_setup_blocks(n, l, blocks, (const float2 *)A, (BlockConsts *)(w + lay.blocks), s);
+        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "block setup launch: %s", hipGetErrorString(e));
+        TimedLaunch t(s, L1LS_KERNEL_ITERATION);
+        e = launch_fista_blocks(ba, s);
+    } else {
+        if (choice == kAuto) choice = mfma_supports(n, l) ? kMfma : kWave;
+        if (choice == kMfma && !mfma_supports(n, l))
+            return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
         TimedLaunch t(s, L1LS_KERNEL_ITERATION);
         e = choice == kMfma ? launch_fista(fa, opt->precision, 0, s) : launch_fista_wave(fa, s);
     }
@@ -305,6 +317,21 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
 {
     return solve_stack(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, workspace, ws_bytes,
                        stream, kAuto);
+}
+
+l1ls_status l1ls_solve_blocks(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                              const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                              int32_t blocks, const double *draws, l1ls_c32 *X, const l1ls_diag *diag,
+                              void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    if (blocks < 1 || blocks > kMaxBlocks || blocks > l)
+        return fail(L1LS_ERR_INVALID_ARG, "blocks must be in [1, min(64, l)], got %d", blocks);
+    if (n > 64) return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the block form takes n <= 64");
+    if (!draws && p > 0) return fail(L1LS_ERR_INVALID_ARG, "draws is NULL");
+    if (opt && fista_blocks_lds(n, lpad_for(l), blocks) > 64 * 1024)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "block form needs more than 64 KB of LDS per pixel");
+    return solve_stack(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, workspace, ws_bytes,
+                       stream, kBlocks, blocks, draws);
 }
 
 const char *l1ls_status_string(l1ls_status s)

@@ -48,6 +48,22 @@ struct FistaArgs {
     int32_t backtracking, monotone, polish;
 };
 
+// Per-block constants of the block-coordinate form (J <= kMaxBlocks).
+constexpr int kMaxBlocks = 64;
+struct BlockConsts {
+    double L;       // 2 lambda_max(A_i A_i^H)
+    double alpha0;  // 1 / (2 max_{l in i} ||a_l||^2)
+    double afloor;  // 1 / L
+    double pad;
+};
+
+struct BlocksArgs {
+    FistaArgs f;           // work[0] accumulates the iteration's FP32 flops
+    int J;
+    const double *u;       // draws in [0, 1), one per iteration
+    const BlockConsts *bc;
+};
+
 struct CertifyArgs {
     int n, l, l_pad;
     int64_t p;
@@ -89,7 +105,7 @@ struct PolishArgsDev {
 
 // Workspace layout for one stack.
 struct StackWorkspace {
-    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, total;
+    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, total;
 };
 StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
 
@@ -104,15 +120,19 @@ hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, fl
                         hipStream_t s);
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s);
 hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s);
+hipError_t launch_setup_blocks(int n, int l, int J, const float2 *A, BlockConsts *bc, hipStream_t s);
+hipError_t launch_fista_blocks(const BlocksArgs &ba, hipStream_t s);
+size_t fista_blocks_lds(int n, int l_pad, int J);
 size_t fista_wave_lds(int n, int l);
 
 // Which iteration kernel runs a stack.
-enum KernelChoice { kAuto = 0, kMfma = 1, kWave = 2 };
+enum KernelChoice { kAuto = 0, kMfma = 1, kWave = 2, kBlocks = 3 };
 bool mfma_supports(int n, int l);
 l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
                         const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
                         l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
-                        hipStream_t s, int choice);
+                        hipStream_t s, int choice, int blocks = 0,
+                        const double *draws = nullptr);
 l1ls_status set_error(l1ls_status st, const char *fmt, ...);
 hipError_t launch_certify(const CertifyArgs &a, hipStream_t s);
 hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s);

@@ -210,3 +210,11 @@ def to_device_dtypes(A, B, lam):
     """Round once to the GPU's storage types (complex64 / float32)."""
     return (np.ascontiguousarray(A, np.complex64), np.ascontiguousarray(B, np.complex64),
             np.ascontiguousarray(lam, np.float32))
+
+
+def uniform_draws(count: int, seed: int = 0) -> np.ndarray:
+    """`count` uniform float64 draws in [0, 1) (the random numbers a randomized
+    block method consumes, one per iteration), from the same keyed Philox stream
+    family as the stacks."""
+    g = np.random.Generator(np.random.Philox(key=KEY + 9000 + seed))
+    return g.random(count)
