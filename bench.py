@@ -150,6 +150,64 @@ def bench_batched(args):
                                   "ms_per_step": o_dt / args.steps * 1e3}}), flush=True)
 
 
+def bench_blocks(args):
+    """Algorithm 1 with J column blocks (Eqs. (13)-(14)) on the scene stack, one
+    shared sequence of seeded draws; the same number of block sweeps (12 J block
+    iterations) before the FP64 stage.  Compared with the one-block solver."""
+    import torch
+    from paper_1805_01759_amd import api, synth
+    cfg, desc = WORKLOADS["scene"]
+    spec, geom, B, lam = synth.make_config(cfg, 0, args.pixels or None)
+    A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
+    dev = torch.device("cuda:0")
+    Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
+    n, l = A32.shape
+    p = B32.shape[0]
+    J = args.blocks
+    cap = args.polish_after * J
+    ud = torch.from_numpy(synth.uniform_draws(max(cap, 1), seed=J)).to(dev)
+    X = torch.empty((p, l), dtype=torch.complex64, device=dev)
+    ws = api.Workspace()
+
+    def timed(**kw):
+        for _ in range(args.warmup):
+            api.solve(Ad, Bd, ld, out=X, workspace=ws, **kw)
+        api.timing_enable(True)
+        for kc in ("iteration", "refine", "certify"):
+            api.timing_read(kc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = []
+        for _ in range(args.steps):
+            _, d = api.solve(Ad, Bd, ld, out=X, workspace=ws, **kw)
+            st.append(d["status"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = {kc: api.timing_read(kc) for kc in ("iteration", "refine", "certify")}
+        api.timing_enable(False)
+        solved = sum(int(((x & 1) != 0).sum().item()) for x in st)
+        fl = api.solve_counters(n, l, p, d)[0]
+        return solved / dt, dt / args.steps * 1e3, solved / (p * args.steps), \
+            {kc: ms / max(c, 1) for kc, (ms, c) in kt.items()}, fl
+
+    base = dict(max_iter=args.max_iter, tol=1e-4, fp64_polish=args.polish)
+    v, ms, sf, kms, fl = timed(blocks=J, draws=ud, polish_after=cap, **base)
+    v1, ms1, sf1, kms1, _ = timed(blocks=1, draws=ud, polish_after=args.polish_after, **base)
+    vm, msm, sfm, kmsm, _ = timed(polish_after=args.polish_after, **base)
+    it_s = kms["iteration"] / 1e3
+    print(json.dumps({
+        "metric": METRIC, "value": v, "unit": "pixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc + f"; Algorithm 1 with J={J} column blocks", "blocks": J,
+                   "block_iterations_before_fp64": cap, "solved_fraction": sf, "kernel_ms": kms,
+                   "iteration_tflops": fl / it_s / 1e12 if it_s > 0 else None},
+        "compare": {"one_block_same_kernel": {"value": v1, "ms_per_step": ms1, "solved_fraction": sf1,
+                                              "kernel_ms": kms1},
+                    "one_block_mfma_solver": {"value": vm, "ms_per_step": msm, "solved_fraction": sfm,
+                                              "kernel_ms": kmsm}}}), flush=True)
+
+
 def bench_unrolled(args):
     """Differentiation through K = 200 unrolled fixed-step iterations (N=25, L=256,
     P=2^18, checkpoints every 20): forward + hand-written adjoint per step."""
@@ -219,7 +277,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="scene", choices=sorted(WORKLOADS) + ["unrolled", "batched"])
+    ap.add_argument("--workload", default="scene", choices=sorted(WORKLOADS) + ["unrolled", "batched", "blocks"])
+    ap.add_argument("--blocks", type=int, default=4, help="J for --workload blocks")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
     ap.add_argument("--max-iter", type=int, default=500)
     ap.add_argument("--polish-after", type=int, default=POLISH_AFTER)
@@ -250,6 +309,8 @@ def main():
         return bench_unrolled(args)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "blocks":
+        return bench_blocks(args)
     cfg, desc = WORKLOADS[args.workload]
     spec, geom, B, lam = synth.make_config(cfg, 0, args.pixels or None)
     A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
