@@ -48,7 +48,7 @@ __host__ __device__ inline int block_width(int l, int J) { return (l + J - 1) / 
 size_t fista_blocks_lds(int n, int l_pad, int J)
 {
     const int w = block_width(l_pad, J);
-    return (size_t)(2 * l_pad + 3 * w + 3 * n + (size_t)J * n) * sizeof(float2) + (size_t)J * 2 * sizeof(float);
+    return (size_t)(2 * l_pad + 3 * w + 2 * n + (size_t)J * n) * sizeof(float2) + (size_t)J * 2 * sizeof(float);
 }
 
 // Per-block constants: one workgroup per block.  L_i = 2 lambda_max(A_i A_i^H)
@@ -158,8 +158,7 @@ __global__ void __launch_bounds__(64) fista_blocks_kernel(const BlocksArgs ba)
     float2 *sd = sg + w;                            // d = x-bar - y on the block
     float2 *sr = sd + w;                            // r = A x - b (n)
     float2 *sry = sr + n;                           // r(y)
-    float2 *sw = sry + n;                           // A_i d
-    float2 *sdr = sw + n;                           // Dr per block (J n)
+    float2 *sdr = sry + n;                          // Dr per block (J n)
     float *sal = reinterpret_cast<float *>(sdr + (size_t)J * n);  // step per block (J)
     int *scnt = reinterpret_cast<int *>(sal + J);                  // updates per block (J)
 
