@@ -701,7 +701,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                 // Newton direction; shifted retries while the Hessian is not PD
                 double mu = 0.0, dv = 0.0;
                 bool ok = false;
-                if (m2 <= 10) build_hessian(sh, s, lam, 0.0);
+                if (m2 <= 16) build_hessian(sh, s, lam, 0.0);
                 for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
                     fl += (unsigned long long)(m2 * m2 * m2 / 3 + 2 * m2 * m2);
                     if (m2 <= 4) {
@@ -712,6 +712,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                         ok = newton_regs<8>(sh, m2, mu, dv);
                     } else if (m2 <= 10) {
                         ok = newton_regs<10>(sh, m2, mu, dv);
+                    } else if (m2 <= 12) {
+                        ok = newton_regs<12>(sh, m2, mu, dv);
+                    } else if (m2 <= 16) {
+                        ok = newton_regs<16>(sh, m2, mu, dv);
                     } else {
                         build_hessian(sh, s, lam, mu);
                         ok = cholesky(sh, m2);
