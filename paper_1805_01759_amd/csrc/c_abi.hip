@@ -63,6 +63,8 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     off = align_up(off + (size_t)p * sizeof(int32_t), 256);
     w.blocks = off;
     off = align_up(off + (size_t)kMaxBlocks * sizeof(BlockConsts), 256);
+    w.resid = off;
+    off = align_up(off + (size_t)p * n * sizeof(float2), 256);
     w.total = off;
     return w;
 }
@@ -193,6 +195,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     fa.polish_count = queue + 1;
     fa.polish_list = plist;
     fa.work = work;
+    fa.R = nullptr;
     int cap = opt->max_iter;
     if (opt->polish_after > 0 && opt->polish_after < cap) cap = opt->polish_after;
     fa.fista_cap = cap;
@@ -215,8 +218,12 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         if (choice == kAuto) choice = mfma_supports(n, l) ? kMfma : kWave;
         if (choice == kMfma && !mfma_supports(n, l))
             return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
+        // the split re/im MFMA kernels keep the residual of each retired pixel
+        bool keeps = false;
+        if (choice == kMfma) fa.R = (float2 *)(w + lay.resid);
         TimedLaunch t(s, L1LS_KERNEL_ITERATION);
-        e = choice == kMfma ? launch_fista(fa, opt->precision, 0, s) : launch_fista_wave(fa, s);
+        e = choice == kMfma ? launch_fista(fa, opt->precision, 0, s, &keeps) : launch_fista_wave(fa, s);
+        if (!keeps) fa.R = nullptr;
     }
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
 
@@ -234,6 +241,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         pa.count = queue + 1;
         pa.next = queue + 2;
         pa.list = plist;
+        pa.R = fa.R;
         pa.status = status_ws;
         pa.rounds = 64;
         pa.mode = opt->fp64_polish;

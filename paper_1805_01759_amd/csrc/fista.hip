@@ -230,9 +230,14 @@ static hipError_t launch_mfma_t(const FistaArgs &a, int max_groups, hipStream_t 
                : launch_mfma_one<T, 8, false, L1LS_FP32, 4>(a, max_groups, s);
 }
 
-hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s)
+hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s, bool *keeps_residual)
 {
     const int T = rows_pad_for(a.n) / 16;
+    // the split re/im kernels (fista_mfma.h) write a.R; the real-embedded ones do not
+    if (keeps_residual)
+        *keeps_residual = precision == L1LS_SPLIT_BF16
+                              ? (slice_blocks_for(a.l) == 8 && mfma_lds_fits(a, L1LS_SPLIT_BF16) && T <= 4)
+                              : T <= 4;
     if (precision == L1LS_SPLIT_BF16) {
         // split re/im layout with bf16 planes in LDS where they fit (64 unknowns per
         // wave); otherwise the real-embedded kernel

@@ -618,7 +618,17 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
             if (fail) alpha = fmaxf(a.c_alpha * alpha, afloor);
         }
 
-        // ---- retire: write x^k of the wave's unknowns
+        // ---- retire: write x^k of the wave's unknowns (and, from wave 0, its residual)
+        if (retire && a.R && w == 0) {
+            float2 *Ro = a.R + (size_t)pix * n;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int nn = 16 * t + 4 * h + q;
+                    if (nn < n) Ro[nn] = make_float2(Rr[t][q], Ri[t][q]);
+                }
+        }
         if (retire) {
             float2 *Xo = a.X + (size_t)pix * l;
 #pragma unroll

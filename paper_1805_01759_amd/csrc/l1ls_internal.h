@@ -43,6 +43,7 @@ struct FistaArgs {
     uint32_t *polish_count;   // number of pixels appended to polish_list
     unsigned long long *work; // [0] pixel forward products, [1] pixel adjoint products, [2] refinement flops
     int32_t *polish_list;
+    float2 *R;                // p x n: residual A x - b of the returned x (FP32), or null
     int32_t fista_cap;        // retire unsolved pixels after this many iterations
     float tol, c_alpha;
     int32_t backtracking, monotone, polish;
@@ -96,6 +97,7 @@ struct PolishArgsDev {
     const uint32_t *count;    // number of listed pixels
     uint32_t *next;           // next list entry to take (zero before the launch)
     const int32_t *list;      // pixel indices
+    const float2 *R;          // p x n residual the iteration kept (FP32), or null
     uint32_t *status;         // workspace status: POLISHED is or-ed in
     unsigned long long *work; // [2] accumulates the refinement's FP64 flops
     int32_t rounds;
@@ -105,7 +107,7 @@ struct PolishArgsDev {
 
 // Workspace layout for one stack.
 struct StackWorkspace {
-    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, total;
+    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid, total;
 };
 StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
 
@@ -118,7 +120,8 @@ int rows_pad_for(int n);       // rows of the packed A: N rounded up to 16
 hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, float2 *At, double2 *gram,
                         StackConsts *consts, uint32_t *queue, unsigned long long *work,
                         hipStream_t s);
-hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s);
+hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s,
+                        bool *keeps_residual = nullptr);
 hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s);
 hipError_t launch_setup_blocks(int n, int l, int J, const float2 *A, BlockConsts *bc, hipStream_t s);
 hipError_t launch_fista_blocks(const BlocksArgs &ba, hipStream_t s);

@@ -534,14 +534,29 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         for (int m = lane; m < a.l_pad; m += 64) sh.sidx[m] = -1;
         if (lane == 0) sh.sb = -1;
         __syncthreads();
-        // objective and FP64 natural KKT residual of the starting point (the
-        // point with the least objective so far is kept in X itself)
-        residual_start(a, sh, b, xo);
-        fl += f8n * (unsigned long long)sh.cnt;
         double fbest;
-        if (a.mode == 1 && (a.status[p] & L1LS_PX_MAX_ITER) != 0) {
+        if (a.mode == 1 && (a.status[p] & L1LS_PX_MAX_ITER) != 0 && a.R) {
             // the FP32 stage's own KKT test failed: the pixel is refined, and only
-            // the objective of the starting point is needed
+            // the objective of the starting point is needed, from the residual
+            // that stage kept and ||x0||_1.  That residual is carried by recursion
+            // in FP32 and drifts (about 1e-6 relative after tens of iterations),
+            // more than F(x0) - F* of a pixel that only just missed tol; the
+            // starting point is a guard against a failed refinement, so its
+            // estimate is raised by a margin well above that drift
+            const float2 *rp = a.R + (size_t)p * a.n;
+            double acc = 0.0;
+            for (int nn = lane; nn < a.n; nn += 64) {
+                const float2 rv = rp[nn];
+                acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            }
+            for (int m = lane; m < a.l; m += 64) {
+                const float2 v = xo[m];
+                acc += lam * sqrt((double)v.x * v.x + (double)v.y * v.y);
+            }
+            fbest = wsum(acc) * (1.0 + 1e-3);
+        } else if (a.mode == 1 && (a.status[p] & L1LS_PX_MAX_ITER) != 0) {
+            residual_start(a, sh, b, xo);
+            fl += f8n * (unsigned long long)sh.cnt;
             double acc = 0.0;
             for (int nn = lane; nn < a.n; nn += 64) acc += sh.r[nn].x * sh.r[nn].x + sh.r[nn].y * sh.r[nn].y;
             for (int q = lane; q < sh.cnt; q += 64) {
@@ -550,6 +565,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             }
             fbest = wsum(acc);
         } else {
+            // objective and FP64 natural KKT residual of the starting point
+            residual_start(a, sh, b, xo);
+            fl += f8n * (unsigned long long)sh.cnt;
             double kk0;
             int vdummy;
             // FP64 throughout: this decides "already solved" against tol itself
