@@ -50,7 +50,7 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     w.consts = off;
     off = align_up(off + sizeof(StackConsts), 256);
     w.queue = off;
-    off = align_up(off + 4 * sizeof(uint32_t), 256);
+    off = align_up(off + 8 * sizeof(uint32_t), 256);
     w.work = off;
     off = align_up(off + 4 * sizeof(unsigned long long), 256);
     w.status = off;
@@ -65,6 +65,8 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     off = align_up(off + (size_t)kMaxBlocks * sizeof(BlockConsts), 256);
     w.resid = off;
     off = align_up(off + (size_t)p * n * sizeof(float2), 256);
+    w.overflow = off;
+    off = align_up(off + (size_t)p * sizeof(int32_t), 256);
     w.total = off;
     return w;
 }
@@ -242,6 +244,8 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         pa.next = queue + 2;
         pa.list = plist;
         pa.R = fa.R;
+        pa.overflow = (int32_t *)(w + lay.overflow);
+        pa.overflow_count = queue + 3;
         pa.status = status_ws;
         pa.rounds = 64;
         pa.mode = opt->fp64_polish;
@@ -253,6 +257,17 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         TimedLaunch t(s, L1LS_KERNEL_REFINE);
         e = launch_polish(pa, cus * 8, s);
         if (e != hipSuccess) return fail(L1LS_ERR_HIP, "polish launch: %s", hipGetErrorString(e));
+        // pixels whose 16-slot working set filled above tol: the 32-slot pass starts
+        // from the point the first one left in X (its FP64 objective is recomputed)
+        PolishArgsDev pw = pa;
+        pw.count = queue + 3;
+        pw.next = queue + 4;
+        pw.list = pa.overflow;
+        pw.R = nullptr;
+        pw.overflow = nullptr;
+        pw.overflow_count = nullptr;
+        e = launch_polish_wide(pw, cus * 4, s);
+        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "wide polish launch: %s", hipGetErrorString(e));
     }
 
     CertifyArgs ca;

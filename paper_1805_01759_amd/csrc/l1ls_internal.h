@@ -98,6 +98,8 @@ struct PolishArgsDev {
     uint32_t *next;           // next list entry to take (zero before the launch)
     const int32_t *list;      // pixel indices
     const float2 *R;          // p x n residual the iteration kept (FP32), or null
+    int32_t *overflow;        // pixels left unsolved on a full working set (or null)
+    uint32_t *overflow_count;
     uint32_t *status;         // workspace status: POLISHED is or-ed in
     unsigned long long *work; // [2] accumulates the refinement's FP64 flops
     int32_t rounds;
@@ -107,7 +109,8 @@ struct PolishArgsDev {
 
 // Workspace layout for one stack.
 struct StackWorkspace {
-    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid, total;
+    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid,
+        overflow, total;
 };
 StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
 
@@ -138,7 +141,8 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
                         const double *draws = nullptr);
 l1ls_status set_error(l1ls_status st, const char *fmt, ...);
 hipError_t launch_certify(const CertifyArgs &a, hipStream_t s);
-hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s);
+hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s);       // 16 slots
+hipError_t launch_polish_wide(const PolishArgsDev &a, int groups, hipStream_t s);  // 32 slots
 size_t unrolled_tape_bytes(int n, int l, int64_t p, int K, int ckpt);
 size_t unrolled_bwd_ws_bytes(int n, int l, int64_t p, int K, int ckpt);
 hipError_t launch_unrolled_forward(int n, int l, int64_t p, const float *xi, const float *s,

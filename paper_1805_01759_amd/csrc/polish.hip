@@ -52,7 +52,13 @@ __device__ __forceinline__ float lane_value_f(float v, int i)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
 }
 
-constexpr int kMaxSupp = 16;          // Newton on at most 16 complex unknowns
+// Newton on at most kMaxSupp complex unknowns: 16 for the first pass; a second
+// build with 32 takes the pixels whose working set filled up before the target
+#ifndef L1LS_POLISH_SUPP
+#define L1LS_POLISH_SUPP 16
+#endif
+constexpr int kMaxSupp = L1LS_POLISH_SUPP;
+static_assert(kMaxSupp == 16 || kMaxSupp == 32, "working sets of 16 or 32 slots");
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
 constexpr int kTri = kMaxM * (kMaxM + 1) / 2;
 constexpr int kGc = kMaxSupp * (kMaxSupp + 1) / 2;
@@ -317,10 +323,11 @@ __device__ void gram_entries(const PolishArgsDev &a, PolishShared &sh, int e0, i
 __device__ void gram_drop(PolishShared &sh, int s, int t)
 {
     const int lane = threadIdx.x;
+    constexpr int KD = ((kMaxSupp - 1) * kMaxSupp / 2 + 63) / 64;  // entries per lane
     const int ne = (s - 1) * s / 2;
-    double2 v[2];
+    double2 v[KD];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KD; ++k) {
         const int e = lane + 64 * k;
         v[k] = make_double2(0.0, 0.0);
         if (e < ne) {
@@ -332,7 +339,7 @@ __device__ void gram_drop(PolishShared &sh, int s, int t)
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < KD; ++k)
         if (lane + 64 * k < ne) sh.Gc[lane + 64 * k] = v[k];
     __syncthreads();
 }
@@ -673,25 +680,29 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         // z += t d by r += t A_S d, c += t G d and the change the line search
         // measured, a drop or an entry by the column's rank-one term.
         bool fresh = true;
+        bool full = false;  // stopped on a full working set above tol
         double ph = 0.0;
         for (int round = 0; round < a.rounds; ++round) {
             for (int it = 0; it < 50 && s > 0; ++it) {
                 const int m2 = 2 * s;
                 if (fresh) {
                     ph = phi_support(a, sh, b0, b1, sh.z, s, lam);
-                    // c = A_S^H r (4 lane groups over the rows of A_S)
-                    const int t = lane & 15, q = lane >> 4;
+                    // c = A_S^H r (64 / kMaxSupp lane groups over the rows of A_S)
+                    constexpr int NG = 64 / kMaxSupp;
+                    const int t = lane % kMaxSupp, q = lane / kMaxSupp;
                     double gr = 0.0, gi = 0.0;
                     if (t < s) {
 #pragma unroll 4
-                        for (int nn = q; nn < a.n; nn += 4) {
+                        for (int nn = q; nn < a.n; nn += NG) {
                             const double2 av = ASat(sh, nn, t), rv = sh.r[nn];
                             gr += av.x * rv.x + av.y * rv.y;
                             gi += av.x * rv.y - av.y * rv.x;
                         }
                     }
-                    gr += __shfl_xor(gr, 16, 64);
-                    gi += __shfl_xor(gi, 16, 64);
+                    if (NG == 4) {
+                        gr += __shfl_xor(gr, 16, 64);
+                        gi += __shfl_xor(gi, 16, 64);
+                    }
                     gr += __shfl_xor(gr, 32, 64);
                     gi += __shfl_xor(gi, 32, 64);
                     if (t < s && q == 0) sh.c[t] = make_double2(gr, gi);
@@ -886,7 +897,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = -1;
             __syncthreads();
             if (kk <= kstop) break;
-            if (vidx < 0 || s >= kMaxSupp) break;
+            if (vidx < 0) break;
+            if (s >= kMaxSupp) {
+                // the working set is full and the point is not solved: a wider pass
+                // takes the pixel from its best point so far
+                full = kk > (double)a.tol;
+                break;
+            }
             // the worst violator enters at its exact coordinate minimiser
             // (lanes over rows: the column is staged and a^H r, ||a||^2 formed at once)
             double gr = 0.0, gi = 0.0, cn = 0.0;
@@ -948,7 +965,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             __syncthreads();
             for (int t = lane; t < sb; t += 64) sh.sidx[sh.Sb[t]] = -1;
         }
-        if (lane == 0) a.status[p] |= L1LS_PX_POLISHED;
+        if (lane == 0) {
+            a.status[p] |= L1LS_PX_POLISHED;
+            if (full && a.overflow) a.overflow[atomicAdd(a.overflow_count, 1u)] = (int32_t)p;
+        }
         __syncthreads();
     }
     if (lane == 0 && fl) atomicAdd(&a.work[2], fl);
