@@ -29,6 +29,11 @@ WORKLOADS = {
     "tiny": (1, "tiny TomoSAR stack: N=15, L=101, P=1024, SNR 10 dB"),
     "pairs": (4, "close-pair TomoSAR stack: N=50, L=512, P=4194304, 40% two scatterers 0.3-1.0 "
                  "Rayleigh apart, SNR 10 dB"),
+    "motion": (6, "multicomponent TomoSAR stack (elevation x linear velocity): N=50 acquisitions over "
+                  "3 years, 32 elevation bins on [-60, 60] m x 16 velocity bins on [-40, 40] mm/yr "
+                  "(L=512), P=524288, 0/1/2 scatterers (0.3/0.5/0.2) at off-grid (s, v), SNR U[0,20] dB"),
+    "motion_fine": (7, "multicomponent TomoSAR stack as 'motion' with 64 elevation bins (L=1024), "
+                       "P=65536"),
 }
 
 
@@ -283,7 +288,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=500)
     ap.add_argument("--polish-after", type=int, default=POLISH_AFTER)
     ap.add_argument("--polish", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle pixels timed for cpu_baseline (0: 16384 at N L = 25 x 256, scaled by 1/(N L))")
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -312,7 +318,10 @@ def main():
     if args.workload == "blocks":
         return bench_blocks(args)
     cfg, desc = WORKLOADS[args.workload]
-    spec, geom, B, lam = synth.make_config(cfg, 0, args.pixels or None)
+    if cfg in synth.MOTION_SPECS:
+        spec, geom, B, lam = synth.make_motion_config(cfg, 0, args.pixels or None)
+    else:
+        spec, geom, B, lam = synth.make_config(cfg, 0, args.pixels or None)
     A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
     dev = torch.device("cuda:0")
     Ad = torch.from_numpy(A32).to(dev)
@@ -344,7 +353,10 @@ def main():
     fwd, adj, npol, pflops = api.solve_counters(n, l, p, d)
     avg_s = {kc: (ms / max(c, 1)) / 1e3 for kc, (ms, c) in kt.items()}
     # iteration kernel: algorithmic flops = (forward + adjoint products) x 8 N L
-    it_kernel = "fista_mfma_kernel" if args.precision == "fp32" else "fista_mfma_kernel_bf16"
+    if n <= 64 and l <= 512:
+        it_kernel = "fista_mfma_kernel" if args.precision == "fp32" else "fista_mfma_kernel_bf16"
+    else:
+        it_kernel = "fista_wave_kernel"
     it_flops = (fwd + adj) * 8.0 * n * l
     it_ach = it_flops / avg_s["iteration"]
     roof_it = {"bound": "mfma", "achieved": it_ach / 1e12, "peak": PEAK[args.precision] / 1e12,
@@ -410,7 +422,9 @@ def main():
                       "solved_fraction": o_solved / (p * args.steps),
                       "kernel_ms": {kc: (ms / max(c, 1)) for kc, (ms, c) in o_kt.items()}}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(A32, B32, l32, min(args.cpu_sample, p), args.max_iter, 1e-4)
+        # about 10-30 s of oracle work: fewer pixels where a pixel costs more
+        sample = args.cpu_sample if args.cpu_sample else max(1024, (16384 * 25 * 256) // (n * l))
+        rec["cpu_baseline"] = cpu_baseline(A32, B32, l32, min(sample, p), args.max_iter, 1e-4)
     print(json.dumps(rec), flush=True)
 
 

@@ -218,3 +218,120 @@ def uniform_draws(count: int, seed: int = 0) -> np.ndarray:
     family as the stacks."""
     g = np.random.Generator(np.random.Philox(key=KEY + 9000 + seed))
     return g.random(count)
+
+
+# ------------------------------------------------ multicomponent (D-TomoSAR) stacks
+#
+# Eqs. (3)-(4): with linear motion the phase of a scatterer at elevation s moving
+# at velocity v (line of sight) is 2 pi (xi_n s + eta_n v), eta_n = 2 t_n / lambda_w
+# for acquisition times t_n; the unknown becomes a profile over the elevation x
+# velocity grid and A gains one column per grid point.  Column c = i + Ls j holds
+# exp(-j 2 pi (xi_n s_i + eta_n v_j)) (elevation the fast index), i.e. A is the
+# column-wise Kronecker product of the elevation and velocity steering matrices.
+
+@dataclasses.dataclass
+class MotionSpec:
+    cfg: int
+    n: int
+    ls: int               # elevation bins
+    lv: int               # velocity bins
+    p: int
+    bmax: float = 300.0   # baselines U[-bmax, bmax] m
+    years: float = 3.0    # acquisition times U[0, years]
+    s_lo: float = -60.0
+    s_hi: float = 60.0
+    v_lo: float = -0.04   # m / year
+    v_hi: float = 0.04
+
+    @property
+    def l(self) -> int:
+        return self.ls * self.lv
+
+
+@dataclasses.dataclass
+class MotionGeometry:
+    n: int
+    ls: int
+    lv: int
+    baselines: np.ndarray  # (N,) m
+    times: np.ndarray      # (N,) years, ascending
+    xi: np.ndarray         # (N,) cycles per metre of elevation
+    eta: np.ndarray        # (N,) cycles per (metre / year) of velocity
+    s: np.ndarray          # (Ls,) elevation grid, m
+    v: np.ndarray          # (Lv,) velocity grid, m / year
+    A: np.ndarray          # (N, Ls Lv) complex128
+
+    @property
+    def l(self) -> int:
+        return self.ls * self.lv
+
+
+MOTION_SPECS = {
+    # N = 50 acquisitions over three years; 32 elevation x 16 velocity bins (L = 512)
+    6: MotionSpec(6, 50, 32, 16, 1 << 19),
+    # the same stack on a finer elevation grid: 64 x 16 = 1024 bins
+    7: MotionSpec(7, 50, 64, 16, 1 << 16),
+}
+
+
+def motion_steering(geom: MotionGeometry, s: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """exp(-j 2 pi (xi_n s + eta_n v)) for arrays s, v of one shape (..., ) -> (..., N)."""
+    return np.exp(-2j * np.pi * (np.multiply.outer(s, geom.xi) + np.multiply.outer(v, geom.eta)))
+
+
+def make_motion_geometry(spec: MotionSpec, stack: int = 0) -> MotionGeometry:
+    g = _gen(spec.cfg, stack, 0, 0)
+    b = g.uniform(-spec.bmax, spec.bmax, size=spec.n)
+    t = np.sort(g.uniform(0.0, spec.years, size=spec.n))
+    xi = 2.0 * b / (WAVELENGTH * RANGE)
+    eta = 2.0 * t / WAVELENGTH
+    s = np.linspace(spec.s_lo, spec.s_hi, spec.ls)
+    v = np.linspace(spec.v_lo, spec.v_hi, spec.lv)
+    ss, vv = np.meshgrid(s, v)            # (Lv, Ls): column c = i + Ls j
+    geom = MotionGeometry(spec.n, spec.ls, spec.lv, b, t, xi, eta, s, v, None)
+    geom.A = np.ascontiguousarray(motion_steering(geom, ss.ravel(), vv.ravel()).T)
+    return geom
+
+
+def _motion_block_pixels(spec: MotionSpec, geom: MotionGeometry, block: int, count: int, stack: int):
+    """Pixels [block*BLOCK, block*BLOCK + count): 0/1/2 scatterers (0.3/0.5/0.2)
+    at off-grid (elevation, velocity), CN(0, 1) amplitudes, SNR U[0, 20] dB."""
+    g = _gen(spec.cfg, stack, 1, block)
+    amp = _cn(g, (count, 2))
+    elev = g.uniform(spec.s_lo, spec.s_hi, size=(count, 2))
+    vel = g.uniform(spec.v_lo, spec.v_hi, size=(count, 2))
+    k = g.choice(3, size=count, p=[0.3, 0.5, 0.2])
+    amp = amp * (np.arange(2)[None, :] < k[:, None])
+    snr = g.uniform(0.0, 20.0, size=count)
+    sigma2 = 10.0 ** (-snr / 10.0)
+    noise = _cn(g, (count, spec.n)) * np.sqrt(sigma2)[:, None]
+    B = np.einsum("pk,pkn->pn", amp, motion_steering(geom, elev, vel)) + noise
+    lam = np.sqrt(sigma2) * math.sqrt(2.0 * spec.n * math.log(spec.l))
+    meta = {"k": k, "elev": elev, "vel": vel, "amp": amp, "snr_db": snr}
+    return B, lam, meta
+
+
+def make_motion_config(cfg: int, p0: int = 0, p1: int | None = None, with_meta: bool = False,
+                       p_override: int | None = None):
+    """Spec, geometry, B (P, N) complex128 and lambda (P,) of pixels [p0, p1) of a
+    multicomponent stack (configuration 6 or 7)."""
+    spec = dataclasses.replace(MOTION_SPECS[cfg])
+    if p_override is not None:
+        spec.p = p_override
+    geom = make_motion_geometry(spec)
+    p1 = spec.p if p1 is None else p1
+    Bs, lams, metas = [], [], []
+    for blk in range(p0 // BLOCK, (p1 - 1) // BLOCK + 1 if p1 > p0 else p0 // BLOCK):
+        start = blk * BLOCK
+        cnt = min(BLOCK, spec.p - start)
+        B, lam, meta = _motion_block_pixels(spec, geom, blk, cnt, 0)
+        lo, hi = max(p0 - start, 0), min(p1 - start, cnt)
+        Bs.append(B[lo:hi])
+        lams.append(lam[lo:hi])
+        metas.append({k: v[lo:hi] for k, v in meta.items()})
+    B = np.concatenate(Bs) if Bs else np.zeros((0, spec.n), np.complex128)
+    lam = np.concatenate(lams) if lams else np.zeros(0)
+    if not with_meta:
+        return spec, geom, B, lam
+    meta = {k: np.concatenate([m[k] for m in metas]) for k in metas[0]} if metas else {}
+    return spec, geom, B, lam, meta

@@ -1,0 +1,112 @@
+"""Multicomponent (elevation x velocity) stacks, Eqs. (3)-(4): GPU solve vs the
+FP64 oracle through the C ABI.
+
+The sensing matrix is the column-wise Kronecker product of the elevation and
+velocity steering matrices (L = Ls x Lv bins); nothing in the solver changes,
+but the grid is far more coherent than an elevation-only one and the minimisers
+carry more nonzeros, so the FP64 stage's second pass (32-slot working sets)
+does real work here.  Checks, as for the scene: the first iterations follow the
+oracle's trajectory; the returned x is judged by its unique parts (the
+certified KKT residual, device vs oracle, and the objective against the
+minimiser's).  A pixel whose minimiser has more than 32 nonzeros is out of the
+FP64 stage's reach and stays unsolved (the FP32 iteration alone stalls above
+tol on this grid): about 17% of the pixels at L = 512 and 4% at L = 1024, so the
+solved-fraction floors below are set under those shares.
+"""
+import numpy as np
+import pytest
+import torch
+
+import bench
+from paper_1805_01759_amd import _lib, api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch.device("cuda:0")
+
+
+def _rel_err(X, Xe, B, Lf):
+    den = np.maximum(np.linalg.norm(Xe, axis=1), np.linalg.norm(B, axis=1) / np.sqrt(Lf / 2))
+    return np.linalg.norm(X - Xe, axis=1) / den
+
+
+def _stack(cfg, p):
+    spec, geom, B, lam = synth.make_motion_config(cfg, 0, p, p_override=max(p, 1))
+    return synth.to_device_dtypes(geom.A, B, lam)
+
+
+def _check(orc, A32, B32, l32, X, d, idx, bar, min_solved):
+    A64 = A32.astype(np.complex128)
+    Lf = orc.lipschitz(A64)
+    Bs = B32[idx].astype(np.complex128)
+    ls = l32[idx].astype(np.float64)
+    Xe, de = orc.exact_batch(A64, Bs, ls)
+    it = torch.from_numpy(idx).to(X.device)
+    Xg = X[it].cpu().numpy().astype(np.complex128)
+    kg = d["kkt"][it].cpu().numpy()
+    ko = np.array([orc.kkt_nat(A64, Bs[k], ls[k], Xg[k], Lf) for k in range(len(idx))])
+    Fg = np.array([orc.objective(A64, Bs[k], ls[k], Xg[k]) for k in range(len(idx))])
+    Fe = np.array([orc.objective(A64, Bs[k], ls[k], Xe[k]) for k in range(len(idx))])
+    gap = (Fg - Fe) / np.maximum(Fe, 1e-30)
+    conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
+    cs = conv[idx]
+    print(f"solved {conv.mean():.4f} (sample {cs.mean():.4f}); gap of solved max "
+          f"{gap[cs].max() if cs.any() else 0:.1e}; exact nnz p50 {np.median((np.abs(Xe) > 0).sum(1))}")
+    assert conv.mean() >= min_solved
+    assert np.allclose(kg, ko, rtol=1e-5, atol=1e-9)
+    assert (ko[cs] <= 1e-4 * (1 + 1e-5)).all()
+    # a certified point is within the tolerance's objective bar of the minimiser;
+    # no returned point lies below the minimum beyond rounding
+    assert gap.min() >= -1e-12
+    assert gap[cs].max() <= bar
+
+
+@pytest.mark.parametrize("cfg", [6, 7])
+def test_motion_trajectory_parity(dev, orc, cfg):
+    """Five iterations of Algorithm 1 on the motion grid: FP32 device vs FP64 oracle."""
+    A32, B32, l32 = _stack(cfg, 300)
+    Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
+    X, d = api.solve(Ad, Bd, ld, max_iter=5, tol=1e-30, fp64_polish=0)
+    A64, B64, L64 = A32.astype(np.complex128), B32.astype(np.complex128), l32.astype(np.float64)
+    Xo, do = orc.rbpg_batch(A64, B64, L64, tol=1e-30, max_iter=5)
+    e = _rel_err(X.cpu().numpy().astype(np.complex128), Xo, B64, orc.lipschitz(A64))
+    assert np.median(e) < 1e-5
+    assert (e <= 1e-3).mean() >= 0.98
+    assert np.array_equal(d["iters"].cpu().numpy(), do["iters"])
+
+
+@pytest.mark.parametrize("cfg,prec,bar", [(6, "fp32", 1e-4), (6, "split_bf16", 1e-3), (7, "fp32", 1e-4)])
+def test_motion_solve_matches_minimiser(dev, orc, cfg, prec, bar):
+    """Bench settings (FP64 stage after the FP32 budget) on a ragged pixel count."""
+    p = 1000 if cfg == 6 else 333
+    A32, B32, l32 = _stack(cfg, p)
+    Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
+    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, precision=prec, fp64_polish=1,
+                     polish_after=bench.POLISH_AFTER)
+    idx = np.arange(0, p, 5 if cfg == 6 else 3)
+    _check(orc, A32, B32, l32, X, d, idx, bar, min_solved=0.75 if cfg == 6 else 0.85)
+
+
+def test_motion_exact_mode(dev, orc):
+    """Every pixel refined in FP64 (mode 2): the certified pixels are the minimiser's."""
+    A32, B32, l32 = _stack(6, 250)
+    Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
+    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=200, fp64_polish=2)
+    _check(orc, A32, B32, l32, X, d, np.arange(250), 1e-5, min_solved=0.75)
+
+
+def test_motion_full_size(dev, orc):
+    """The bench workload at full size (2^19 pixels, L = 512), sampled."""
+    spec, geom, B, lam = synth.make_motion_config(6)
+    A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
+    del B
+    Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
+    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, fp64_polish=1, polish_after=bench.POLISH_AFTER)
+    p = B32.shape[0]
+    idx = np.arange(13, p, p // 128)
+    _check(orc, A32, B32, l32, X, d, idx, 1e-4, min_solved=0.8)

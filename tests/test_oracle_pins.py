@@ -342,3 +342,21 @@ def test_rbpg_reaches_minimiser(orc):
         assert -1e-12 <= gap <= 1e-8 * max(1.0, d["objective"][p])
     x, info = orc.rbpg(A, B[3], lam[3], tol=1e-4, max_iter=5)
     assert info["iters"] == 5 and orc.kkt_nat(A, B[3], lam[3], x, Lf) == pytest.approx(info["kkt_nat"])
+
+
+def test_motion_grid_one_scatterer_closed_form(orc):
+    """One on-grid scatterer on the elevation x velocity grid, no noise: every
+    column has ||a||^2 = N and |a_j^H a_i| <= N, so the minimiser is the scalar
+    soft threshold on the true column, (|g| - lambda/(2N)) g/|g|, zero elsewhere."""
+    from paper_1805_01759_amd import synth
+    spec, geom, _, _ = synth.make_motion_config(6, 0, 1)
+    A = geom.A
+    n, l = A.shape
+    for c, g in ((37, 1.3 - 0.4j), (300, -0.2 + 0.9j)):
+        b = A[:, c] * g
+        lam = 0.3 * n
+        X, d = orc.exact_batch(A, b[None, :], np.array([lam]))
+        want = np.zeros(l, complex)
+        want[c] = (abs(g) - lam / (2 * n)) * g / abs(g)
+        assert np.abs(X[0] - want).max() < 1e-9
+        assert d["kkt_nat"][0] < 1e-9

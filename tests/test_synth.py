@@ -64,3 +64,39 @@ def test_config5_on_grid_truth():
     X = synth.xtrue(spec, geom, meta)
     resid = B - X @ geom.A.T
     assert np.abs(resid).std() < 0.5  # only noise remains
+
+
+def test_motion_matrix_is_kronecker_of_steering():
+    """Eqs. (3)-(4): column i + Ls j of A is the elevation steering vector of s_i
+    times the velocity one of v_j (unit modulus)."""
+    spec, geom, B, lam = synth.make_motion_config(6, 0, 64)
+    assert geom.A.shape == (50, 512) and B.shape == (64, 50)
+    Es = np.exp(-2j * np.pi * np.outer(geom.xi, geom.s))
+    Ev = np.exp(-2j * np.pi * np.outer(geom.eta, geom.v))
+    want = (Es[:, None, :] * Ev[:, :, None]).reshape(50, -1)
+    assert np.allclose(geom.A, want, atol=1e-12)
+    assert np.allclose(np.abs(geom.A), 1.0)
+    assert np.all(np.diff(geom.times) >= 0) and geom.times.max() <= 3.0
+    assert np.allclose(lam, np.sqrt(10 ** (-_motion_snr(0, 64) / 10)) * math.sqrt(2 * 50 * math.log(512)))
+
+
+def _motion_snr(p0, p1):
+    return synth.make_motion_config(6, p0, p1, with_meta=True)[4]["snr_db"]
+
+
+def test_motion_subset_reproducible():
+    _, _, B, lam = synth.make_motion_config(6, 0, 9000)
+    _, _, B2, lam2 = synth.make_motion_config(6, 4000, 9000)
+    assert np.array_equal(B[4000:9000], B2) and np.array_equal(lam[4000:9000], lam2)
+
+
+def test_motion_pixels_follow_the_model():
+    """A noiseless-limit check: B minus the scatterers' steering vectors is the
+    noise, whose power matches the drawn SNR."""
+    spec, geom, B, lam, meta = synth.make_motion_config(6, 0, 8000, with_meta=True)
+    sig = np.einsum("pk,pkn->pn", meta["amp"], synth.motion_steering(geom, meta["elev"], meta["vel"]))
+    noise = B - sig
+    ratio = np.mean(np.abs(noise) ** 2, axis=1) / 10 ** (-meta["snr_db"] / 10)
+    assert abs(np.mean(ratio) - 1.0) < 0.02
+    frac = np.bincount(meta["k"], minlength=3) / 8000
+    assert np.allclose(frac, [0.3, 0.5, 0.2], atol=0.02)
