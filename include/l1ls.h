@@ -76,7 +76,10 @@ typedef struct {
     int32_t backtracking;  /* 1: Eq. (15) line search; 0: fixed step 1/L_f                     */
     int32_t monotone;      /* 1: accept x-bar only if F(x-bar) <= F(x^k) (Algorithm 1)         */
     int32_t fp64_polish;   /* FP64 active-set Newton refinement: 0 off; 1 pixels whose FP64
-                              KKT residual exceeds tol; 2 every pixel (to FP64 precision)      */
+                              KKT residual exceeds tol; 2 every pixel (to FP64 precision).
+                              Working sets of up to 16 complex unknowns, then a second pass
+                              with up to 32 for pixels that filled the first; a pixel whose
+                              minimiser has more nonzeros is returned unsolved (status bits) */
     int32_t polish_after;  /* hand a pixel to the refinement after this many iterations
                               (<= max_iter; <= 0 means max_iter)                              */
     int32_t warm_start;    /* reserved, must be 0                                              */

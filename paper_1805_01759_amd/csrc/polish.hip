@@ -680,7 +680,6 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         // z += t d by r += t A_S d, c += t G d and the change the line search
         // measured, a drop or an entry by the column's rank-one term.
         bool fresh = true;
-        bool full = false;  // stopped on a full working set above tol
         double ph = 0.0;
         for (int round = 0; round < a.rounds; ++round) {
             for (int it = 0; it < 50 && s > 0; ++it) {
@@ -900,8 +899,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             if (vidx < 0) break;
             if (s >= kMaxSupp) {
                 // the working set is full and the point is not solved: a wider pass
-                // takes the pixel from its best point so far
-                full = kk > (double)a.tol;
+                // (a later launch) takes the pixel from its best point so far
+                if (a.overflow && kk > (double)a.tol && lane == 0)
+                    a.overflow[atomicAdd(a.overflow_count, 1u)] = (int32_t)p;
                 break;
             }
             // the worst violator enters at its exact coordinate minimiser
@@ -965,10 +965,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             __syncthreads();
             for (int t = lane; t < sb; t += 64) sh.sidx[sh.Sb[t]] = -1;
         }
-        if (lane == 0) {
-            a.status[p] |= L1LS_PX_POLISHED;
-            if (full && a.overflow) a.overflow[atomicAdd(a.overflow_count, 1u)] = (int32_t)p;
-        }
+        if (lane == 0) a.status[p] |= L1LS_PX_POLISHED;
         __syncthreads();
     }
     if (lane == 0 && fl) atomicAdd(&a.work[2], fl);
