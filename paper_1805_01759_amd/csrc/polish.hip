@@ -59,6 +59,9 @@ __device__ __forceinline__ float lane_value_f(float v, int i)
 #endif
 constexpr int kMaxSupp = L1LS_POLISH_SUPP;
 static_assert(kMaxSupp == 16 || kMaxSupp == 32, "working sets of 16 or 32 slots");
+// violators admitted per round: the wide pass grows its set by up to 4 a round
+// (the next-largest violations of distinct lanes), the first pass by one
+constexpr int kEnter = kMaxSupp == 32 ? 4 : 1;
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
 constexpr int kTri = kMaxM * (kMaxM + 1) / 2;
 constexpr int kGc = kMaxSupp * (kMaxSupp + 1) / 2;
@@ -82,6 +85,8 @@ struct PolishShared {
     double2 zb[kMaxSupp];  // the point with the least objective so far, on slots Sb[0..sb)
     int Sb[kMaxSupp];
     int sb;                // -1: the starting point (already in X) is the best
+    int vl[kEnter];        // violators to admit, largest first (full pass, kEnter > 1)
+    int nv;
 };
 
 __device__ __forceinline__ double2 Aat(const PolishArgsDev &a, int n, int m)
@@ -267,6 +272,29 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2
     }
     F = wsum(acc + lam * l1);
     kk = sqrt(wmax(km)) * lf / lam;
+    if constexpr (kEnter > 1) {
+        // the largest violations of distinct lanes, largest first (ties: lowest bin)
+        if (!START) {
+            double vrem = vbest;
+            int nv = 0;
+            for (int e = 0; e < kEnter; ++e) {
+                const double vm = wmax(vrem);
+                if (!(vm > 0.0)) break;
+                uint64_t cl = __ballot(vrem == vm);
+                int bm = -1;
+                while (cl) {
+                    const int ln = __ffsll((unsigned long long)cl) - 1;
+                    cl &= cl - 1;
+                    const int m = __builtin_amdgcn_readlane(vidx, ln);
+                    if (bm < 0 || m < bm) bm = m;
+                }
+                if (vidx == bm) vrem = 0.0;
+                if (lane == 0) sh.vl[nv] = bm;
+                ++nv;
+            }
+            if (lane == 0) sh.nv = nv;
+        }
+    }
     // wave argmax of the violation (ties: lowest bin)
     const double vmax = wmax(vbest);
     uint64_t cand = __ballot(vmax > 0.0 && vbest == vmax);
@@ -904,8 +932,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                     a.overflow[atomicAdd(a.overflow_count, 1u)] = (int32_t)p;
                 break;
             }
-            // the worst violator enters at its exact coordinate minimiser
+            // the worst violator enters at its exact coordinate minimiser (the wide
+            // pass: up to kEnter of them, one after another against the updated r)
             // (lanes over rows: the column is staged and a^H r, ||a||^2 formed at once)
+            const int nv = kEnter > 1 ? sh.nv : 1;
+            int entered = 0;
+            for (int e = 0; e < nv && s < kMaxSupp; ++e) {
+            if (kEnter > 1) vidx = sh.vl[e];
             double gr = 0.0, gi = 0.0, cn = 0.0;
             for (int nn = lane; nn < a.n; nn += 64) {
                 const float2 af = a.A[(size_t)nn * a.l_pad + vidx];
@@ -928,7 +961,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                 sh.z[s] = zn;
             }
             __syncthreads();
-            if (sc == 0.0) break;
+            if (sc == 0.0) continue;  // no longer a violator
+            ++entered;
             ++s;
             gram_entries(a, sh, (s - 1) * s / 2, s * (s + 1) / 2);  // the new row of G
             fl += f8n * (unsigned long long)s;
@@ -952,6 +986,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
                 __syncthreads();
                 fl += f8n + 8ull * (unsigned long long)s;
             }
+            }
+            if (entered == 0) break;
         }
         // write the best point (complex64) unless it is the starting one
         if (sh.sb >= 0) {
