@@ -61,7 +61,7 @@ constexpr int kMaxSupp = L1LS_POLISH_SUPP;
 static_assert(kMaxSupp == 16 || kMaxSupp == 32, "working sets of 16 or 32 slots");
 // violators admitted per round: the wide pass grows its set by up to 4 a round
 // (the next-largest violations of distinct lanes), the first pass by one
-constexpr int kEnter = kMaxSupp == 32 ? 4 : 1;
+constexpr int kEnter = kMaxSupp == 32 ? 8 : 1;
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
 constexpr int kTri = kMaxM * (kMaxM + 1) / 2;
 constexpr int kGc = kMaxSupp * (kMaxSupp + 1) / 2;
