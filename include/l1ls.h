@@ -55,7 +55,9 @@ typedef enum {
  * L1LS_FP32: FP32 MFMA.  L1LS_SPLIT_BF16: every operand split into hi + lo
  * bfloat16 parts, three MFMA passes (hi*hi + hi*lo + lo*hi) with FP32
  * accumulation.  Everything else (prox, step, reductions) is FP32; the
- * refinement and the final optimality check are FP64. */
+ * refinement and the final optimality check are FP64.  Shapes outside the MFMA
+ * kernels (n > 64 or l > 512) run the wave-per-pixel kernel, whose contractions
+ * are plain FP32 vector arithmetic under either setting. */
 typedef enum { L1LS_FP32 = 0, L1LS_SPLIT_BF16 = 1 } l1ls_precision;
 
 /* Per-pixel status bits (diag.status). */
