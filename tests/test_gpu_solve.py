@@ -272,3 +272,24 @@ def test_close_pairs_sampled(dev, orc):
         print(f"{prec}: solved {conv.mean():.4f}; e p50 {np.median(e):.1e} p99 {np.percentile(e, 99):.1e} max {e.max():.1e}")
         assert conv.mean() >= 0.99
         assert (e <= bar).mean() >= 0.98
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp32", 2e-6), ("split_bf16", 2e-4)])
+def test_golden_trajectory_on_device(dev, precision, rtol):
+    """The hand-derived six iterations of Algorithm 1 (tests/golden/algorithm1_trajectory.txt:
+    carried step shrunk once at k = 4, monotone reject at k = 5) through the C ABI, for 64
+    pixels whose b is the golden b rotated by a per-pixel phase (A is real, so x^k rotates too)."""
+    from test_oracle_trajectory import A_G, B_G, LAM_G, golden_rows
+    p = 64
+    rot = np.exp(1j * np.linspace(-3.0, 3.0, p))
+    A32 = A_G.astype(np.complex64)
+    B32 = (B_G[None, :] * rot[:, None]).astype(np.complex64)
+    l32 = np.full(p, LAM_G, np.float32)
+    Ad, Bd, ld = _to_dev(dev, A32, B32, l32)
+    for r in golden_rows():
+        X, d = api.solve(Ad, Bd, ld, max_iter=r["k"], tol=1e-30, fp64_polish=0, precision=precision)
+        want = np.array([float(v) for v in r["x"]])[None, :] * rot[:, None]
+        Xg = X.cpu().numpy().astype(np.complex128)
+        err = np.abs(Xg - want).max()
+        assert err <= rtol * np.abs(want).max(), (r["k"], err)
+        assert (d["iters"].cpu().numpy() == r["k"]).all()
