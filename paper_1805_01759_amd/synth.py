@@ -18,8 +18,10 @@ and the oracle upcasts those same rounded values.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -132,16 +134,28 @@ def _block_pixels(spec: Spec, geom: Geometry, block: int, count: int, stack: int
     return B, lam, meta
 
 
+def _map_blocks(fn, blocks):
+    """fn over pixel blocks; blocks draw from their own counters, so running them
+    on several threads gives the same values as one after another."""
+    if len(blocks) < 8:
+        return [fn(b) for b in blocks]
+    workers = min(16, os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, blocks))
+
+
 def make_pixels(spec: Spec, geom: Geometry, p0: int = 0, p1: int | None = None,
                 stack: int = 0, with_meta: bool = False):
     """B (P, N) complex128 and lambda (P,) float64 for pixels [p0, p1)."""
     p1 = spec.p if p1 is None else p1
     Bs, lams, metas = [], [], []
     b0, b1 = p0 // BLOCK, (p1 - 1) // BLOCK
-    for blk in range(b0, b1 + 1):
+    blocks = list(range(b0, b1 + 1))
+    outs = _map_blocks(lambda blk: _block_pixels(spec, geom, blk, min(BLOCK, spec.p - blk * BLOCK),
+                                                 stack), blocks)
+    for blk, (B, lam, meta) in zip(blocks, outs):
         start = blk * BLOCK
         cnt = min(BLOCK, spec.p - start)
-        B, lam, meta = _block_pixels(spec, geom, blk, cnt, stack)
         lo, hi = max(p0 - start, 0), min(p1 - start, cnt)
         Bs.append(B[lo:hi])
         lams.append(lam[lo:hi])
@@ -321,10 +335,12 @@ def make_motion_config(cfg: int, p0: int = 0, p1: int | None = None, with_meta: 
     geom = make_motion_geometry(spec)
     p1 = spec.p if p1 is None else p1
     Bs, lams, metas = [], [], []
-    for blk in range(p0 // BLOCK, (p1 - 1) // BLOCK + 1 if p1 > p0 else p0 // BLOCK):
+    blocks = list(range(p0 // BLOCK, (p1 - 1) // BLOCK + 1 if p1 > p0 else p0 // BLOCK))
+    outs = _map_blocks(lambda blk: _motion_block_pixels(spec, geom, blk,
+                                                        min(BLOCK, spec.p - blk * BLOCK), 0), blocks)
+    for blk, (B, lam, meta) in zip(blocks, outs):
         start = blk * BLOCK
         cnt = min(BLOCK, spec.p - start)
-        B, lam, meta = _motion_block_pixels(spec, geom, blk, cnt, 0)
         lo, hi = max(p0 - start, 0), min(p1 - start, cnt)
         Bs.append(B[lo:hi])
         lams.append(lam[lo:hi])
