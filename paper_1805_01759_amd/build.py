@@ -3,12 +3,13 @@
 Usage: python -m paper_1805_01759_amd.build [--incremental]   (or build() from Python)
 
 --incremental recompiles only sources whose object is older than the source
-or than any header under csrc/ or include/.
+or than a file it #includes (transitively).
 """
 from __future__ import annotations
 
 import concurrent.futures
 import os
+import re
 import subprocess
 import sys
 
@@ -42,19 +43,30 @@ def _compile(src: str) -> str:
     return obj
 
 
-def _headers_mtime() -> float:
-    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    inc = os.path.join(ROOT, "include")
-    hs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
-    return max(os.path.getmtime(h) for h in hs)
+_INCLUDE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
 
 
-def _stale(src: str, hdr: float) -> bool:
+def _deps(path: str, seen: set) -> set:
+    """`path` and every file it #includes with quotes, transitively (sources
+    that include other .hip files count them too)."""
+    if path in seen:
+        return seen
+    seen.add(path)
+    for name in _INCLUDE.findall(open(path).read()):
+        for base in (os.path.dirname(path), CSRC, os.path.join(ROOT, "include")):
+            cand = os.path.normpath(os.path.join(base, name))
+            if os.path.exists(cand):
+                _deps(cand, seen)
+                break
+    return seen
+
+
+def _stale(src: str) -> bool:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    return t < os.path.getmtime(src) or t < hdr
+    return any(t < os.path.getmtime(d) for d in _deps(src, set()))
 
 
 def build(verbose: bool = False, incremental: bool = False) -> str:
@@ -62,8 +74,7 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     srcs = sources()
     todo = srcs
     if incremental:
-        hdr = _headers_mtime()
-        todo = [s for s in srcs if _stale(s, hdr)]
+        todo = [s for s in srcs if _stale(s)]
     if todo:
         with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
             list(ex.map(_compile, todo))
