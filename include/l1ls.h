@@ -19,8 +19,10 @@
  *  - A is row-major: A[n * L + l].  B is pixel-major: B[p * N + n].
  *    X is pixel-major: X[p * L + l].
  *  - Every pointer named "device" is a HIP device pointer; the caller owns the
- *    memory.  The library allocates no device memory in any entry point below:
- *    scratch lives in the caller's workspace.  Work is queued on the given
+ *    memory.  The solve, plan-execute and unrolled entry points allocate no
+ *    device memory: scratch lives in the caller's workspace (l1ls_solve_noalloc:
+ *    in a fixed array of the library).  l1ls_plan_create allocates temporary
+ *    buffers while it times candidate kernels.  Work is queued on the given
  *    stream and nothing synchronises the host.
  *  - Argument errors are detected on the host before any launch: the call
  *    returns a negative l1ls_status and l1ls_last_error() describes it.
@@ -125,6 +127,27 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
                        const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
                        l1ls_c32 *X, const l1ls_diag *diag, void *workspace, size_t ws_bytes,
                        hipStream_t stream);
+
+/* l1ls_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as l1ls_solve, with the workspace taken from a
+ * fixed array of L1LS_NOALLOC_SCRATCH_BYTES in the library's code object, one
+ * per device, held until the process ends (its address is looked up on the
+ * first call on each device; that lookup is the only set-up).  The caller
+ * passes inputs and outputs as for l1ls_solve; no hipMalloc, hipFree or event
+ * is created.  The stream must belong to the current device.
+ *  - returns L1LS_ERR_WORKSPACE, with no work queued, when l1ls_workspace_size
+ *    for (n, l, p) exceeds L1LS_NOALLOC_SCRATCH_BYTES (e.g. n = 25, l = 256
+ *    holds about 150,000 pixels); split the pixels or call l1ls_solve.
+ *  - every call on one device shares that device's array, which keeps the last
+ *    call's contents (the kernels clear what must start at zero): calls that
+ *    overlap in time on one device race and give undefined results; serialise
+ *    them (one stream, or events).
+ *  - timing events (l1ls_timing_enable) are not recorded for these calls. */
+#define L1LS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+l1ls_status l1ls_solve_noalloc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                               const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                               l1ls_c32 *X, const l1ls_diag *diag, hipStream_t stream);
 
 /* Algorithm 1 with J column blocks (randomized block prox-gradient, Eqs. (13)-(14)).
  * Bins are split into J contiguous blocks of ceil(l/J); iteration k of a pixel

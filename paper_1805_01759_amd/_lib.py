@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "L1LS_OK", -1: "L1LS_ERR_INVALID_ARG", -2: "L1LS_ERR_UNSUPPOR
                 -3: "L1LS_ERR_WORKSPACE", -4: "L1LS_ERR_HIP", -5: "L1LS_ERR_INTERNAL"}
 
 EXPORTS = [
-    "l1ls_options_default", "l1ls_workspace_size", "l1ls_solve", "l1ls_solve_blocks",
+    "l1ls_options_default", "l1ls_workspace_size", "l1ls_solve", "l1ls_solve_noalloc",
+    "l1ls_solve_blocks",
     "l1ls_plan_create", "l1ls_plan_workspace_size", "l1ls_plan_execute", "l1ls_plan_destroy",
     "l1ls_plan_describe",
     "l1ls_unrolled_tape_size", "l1ls_unrolled_backward_ws_size", "l1ls_unrolled_forward",
@@ -31,6 +32,9 @@ EXPORTS = [
 
 # kernel classes for l1ls_timing_read_kernel
 KERNEL_ITERATION, KERNEL_REFINE, KERNEL_CERTIFY = 0, 1, 2
+
+# L1LS_NOALLOC_SCRATCH_BYTES: the fixed scratch of l1ls_solve_noalloc
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class Options(ctypes.Structure):
@@ -75,6 +79,9 @@ def load() -> ctypes.CDLL:
     L.l1ls_solve.argtypes = [I32, I32, I64, P, P, P, I64, ctypes.POINTER(Options), P,
                              ctypes.POINTER(Diag), P, SZ, P]
     L.l1ls_solve.restype = st
+    L.l1ls_solve_noalloc.argtypes = [I32, I32, I64, P, P, P, I64, ctypes.POINTER(Options), P,
+                                     ctypes.POINTER(Diag), P]
+    L.l1ls_solve_noalloc.restype = st
     L.l1ls_solve_blocks.argtypes = [I32, I32, I64, P, P, P, I64, ctypes.POINTER(Options), I32, P, P,
                                     ctypes.POINTER(Diag), P, ctypes.c_size_t, P]
     L.l1ls_solve_blocks.restype = st

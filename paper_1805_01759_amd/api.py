@@ -127,6 +127,25 @@ def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = N
     return X, diag
 
 
+def solve_noalloc(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor,
+                  diag: dict | None = None, stream=None, **opts):
+    """solve() through l1ls_solve_noalloc: no workspace argument, the library's
+    fixed scratch array is used (at most NOALLOC_SCRATCH_BYTES of workspace).
+    X (out) and the diagnostics (a dict as new_diag returns, or None) are the
+    caller's; nothing is allocated on the device here or in the library."""
+    L = _lib.load()
+    A, B, lam_t, stride = _check_inputs(A, B, lam)
+    n, l = A.shape
+    p = B.shape[0]
+    o = options(**opts)
+    d = _lib.Diag(*(diag[k].data_ptr() for k in ("iters", "kkt", "objective", "status", "nnz"))) \
+        if diag is not None else None
+    _lib.check(L.l1ls_solve_noalloc(n, l, p, _ptr(A), _ptr(B), _ptr(lam_t), stride, ctypes.byref(o),
+                                    _ptr(out), ctypes.byref(d) if d is not None else None,
+                                    _stream(stream)), "l1ls_solve_noalloc")
+    return out, diag
+
+
 def solve_counters(n: int, l: int, p: int, diag, stream=None):
     """(forward products, adjoint products, pixels refined, refinement FP64 flops)
     of the solve that made `diag`."""

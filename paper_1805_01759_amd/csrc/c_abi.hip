@@ -121,12 +121,16 @@ static std::mutex g_tmu;
 static bool g_timing = false;
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events[3];
 
+// Calls that must not allocate (l1ls_solve_noalloc) leave the events out.
+static thread_local bool g_no_events = false;
+
 struct TimedLaunch {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t s;
     int cls;
     TimedLaunch(hipStream_t st, int c) : s(st), cls(c)
     {
+        if (g_no_events) return;
         std::lock_guard<std::mutex> g(g_tmu);
         if (!g_timing) return;
         hipEventCreate(&e0);
@@ -298,6 +302,37 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     return L1LS_OK;
 }
 
+// Workspace of l1ls_solve_noalloc: one statically sized array in the code
+// object, so each device the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: its device address is looked up once per device (with that
+// device current) and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[L1LS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];
+
+static l1ls_status scratch_for_current_device(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "device %d beyond the %d devices with scratch", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(L1LS_ERR_HIP, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return L1LS_OK;
+}
+
 }  // namespace l1ls
 
 using namespace l1ls;
@@ -340,6 +375,31 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
 {
     return solve_stack(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, workspace, ws_bytes,
                        stream, kAuto);
+}
+
+l1ls_status l1ls_solve_noalloc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                               const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                               l1ls_c32 *X, const l1ls_diag *diag, hipStream_t stream)
+{
+    l1ls_status st = check_shape(n, l, p);
+    if (st != L1LS_OK) return st;
+    st = check_options(opt);
+    if (st != L1LS_OK) return st;
+    const size_t need = stack_workspace_layout(n, l, p).total;
+    if (need > (size_t)L1LS_NOALLOC_SCRATCH_BYTES)
+        return fail(L1LS_ERR_WORKSPACE,
+                    "l1ls_solve_noalloc: n=%d, l=%d, p=%lld needs %zu bytes of scratch, above its "
+                    "fixed %zu (use l1ls_solve with a workspace)",
+                    n, l, (long long)p, need, (size_t)L1LS_NOALLOC_SCRATCH_BYTES);
+    if (p == 0) return L1LS_OK;
+    void *ws = nullptr;
+    st = scratch_for_current_device(&ws);
+    if (st != L1LS_OK) return st;
+    g_no_events = true;
+    st = solve_stack(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, ws,
+                     (size_t)L1LS_NOALLOC_SCRATCH_BYTES, stream, kAuto);
+    g_no_events = false;
+    return st;
 }
 
 l1ls_status l1ls_solve_blocks(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,

@@ -81,3 +81,16 @@ def test_argument_errors_before_any_launch(L):
 
 def test_empty_batch_is_a_noop(L):
     assert _solve(L, p=0, A=0, B=0, lam=0, X=0, ws=0, wsb=0) == 0
+
+
+def test_noalloc_size_limit_checked_on_host(L):
+    # l1ls_solve_noalloc refuses, before any device call, a stack whose workspace
+    # exceeds its fixed scratch array; the pointers are never read
+    o = L.l1ls_options_default()
+    big = _lib.NOALLOC_SCRATCH_BYTES // (8 * 25)
+    st = L.l1ls_solve_noalloc(25, 256, big, None, None, None, 0, ctypes.byref(o), None, None, None)
+    assert st == -3
+    assert b"scratch" in L.l1ls_last_error()
+    assert L.l1ls_solve_noalloc(25, 256, 10, None, None, None, 0, None, None, None, None) == -1
+    assert L.l1ls_solve_noalloc(200, 256, 10, None, None, None, 0, ctypes.byref(o), None, None,
+                                None) == -2

@@ -1,0 +1,79 @@
+"""l1ls_solve_noalloc (the library's fixed scratch array instead of a caller
+workspace) against l1ls_solve on the same inputs, through the C ABI.
+
+Both calls run the same kernels on the same data, and every pixel's result is
+computed by one tile slot or one workgroup independently of the others, so the
+outputs must agree bit for bit.  Two calls in a row, the second with fewer
+pixels and another shape, check that nothing the first call left in the shared
+array leaks into the second.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1805_01759_amd import _lib, api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(cfg, p, dev):
+    spec, geom, B, lam = synth.make_config(cfg, 0, p)
+    A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
+    return [torch.from_numpy(x).to(dev) for x in (A32, B32, l32)]
+
+
+def _both(A, B, lam, **opts):
+    p, l = B.shape[0], A.shape[1]
+    X0, d0 = api.solve(A, B, lam, workspace=api.Workspace(), **opts)
+    X1 = torch.full((p, l), float("nan"), dtype=torch.complex64, device=B.device)
+    d1 = api.new_diag(p, B.device)
+    for v in d1.values():
+        v.fill_(-7)
+    api.solve_noalloc(A, B, lam, out=X1, diag=d1, **opts)
+    torch.cuda.synchronize()
+    return X0, d0, X1, d1
+
+
+def _same(X0, d0, X1, d1):
+    assert torch.equal(torch.view_as_real(X0), torch.view_as_real(X1))
+    for k in ("iters", "kkt", "objective", "status", "nnz"):
+        assert torch.equal(d0[k], d1[k]), k
+
+
+def test_noalloc_matches_workspace_solve_twice():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    dev = torch.device("cuda:0")
+    print("noalloc: scene stack, 3000 pixels, then close-pair stack, 700 pixels", flush=True)
+    A, B, lam = _inputs(2, 3000, dev)
+    X0, d0, X1, d1 = _both(A, B, lam, polish_after=12)
+    _same(X0, d0, X1, d1)
+    assert ((d1["status"] & 1) != 0).float().mean().item() > 0.99
+    # second call: fewer pixels, another (N, L), scalar lambda, split-BF16
+    A2, B2, lam2 = _inputs(4, 700, dev)
+    X0, d0, X1, d1 = _both(A2, B2, lam2[0].item(), polish_after=12, precision="split_bf16")
+    _same(X0, d0, X1, d1)
+    assert ((d1["status"] & 1) != 0).float().mean().item() > 0.9
+
+
+def test_noalloc_rejects_beyond_its_scratch():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    dev = torch.device("cuda:0")
+    n, l = 25, 256
+    p = _lib.NOALLOC_SCRATCH_BYTES // (8 * n)  # the kept residual alone fills the array
+    assert api.workspace_size(n, l, p) > _lib.NOALLOC_SCRATCH_BYTES
+    A = torch.zeros((n, l), dtype=torch.complex64, device=dev)
+    B = torch.zeros((p, n), dtype=torch.complex64, device=dev)
+    X = torch.zeros((p, l), dtype=torch.complex64, device=dev)
+    with pytest.raises(_lib.L1LSError, match="L1LS_ERR_WORKSPACE"):
+        api.solve_noalloc(A, B, 1.0, out=X)
+    # nothing was queued: X is untouched
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(torch.view_as_real(X))) == 0
+    # p = 0 is a no-op
+    L = _lib.load()
+    o = L.l1ls_options_default()
+    assert L.l1ls_solve_noalloc(n, l, 0, None, None, None, 0, ctypes.byref(o), None, None, None) == 0
