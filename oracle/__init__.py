@@ -47,7 +47,8 @@ _lib = None
 class RbpgOpts(ctypes.Structure):
     _fields_ = [("alpha0", ctypes.c_double), ("c_alpha", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("backtracking", ctypes.c_int), ("monotone", ctypes.c_int)]
+                ("backtracking", ctypes.c_int), ("monotone", ctypes.c_int),
+                ("warm_start", ctypes.c_int)]
 
 
 class RbpgInfo(ctypes.Structure):
@@ -150,13 +151,14 @@ def dual_gap(A, b, lam, x) -> float:
 
 
 def rbpg(A, b, lam, *, tol=1e-4, max_iter=500, c_alpha=0.5, alpha0=0.0,
-         backtracking=True, monotone=True, Lf=None):
-    """Algorithm 1 with one block on a single pixel. Returns (x, info dict)."""
+         backtracking=True, monotone=True, Lf=None, x0=None):
+    """Algorithm 1 with one block on a single pixel, from x^(0) = x0 (default 0).
+    Returns (x, info dict)."""
     A, b = _c128(A), _c128(b)
     n, l = A.shape
     Lf = lipschitz(A) if Lf is None else Lf
-    x = np.zeros(l, np.complex128)
-    o = RbpgOpts(alpha0, c_alpha, tol, max_iter, int(backtracking), int(monotone))
+    x = np.zeros(l, np.complex128) if x0 is None else _c128(x0).copy()
+    o = RbpgOpts(alpha0, c_alpha, tol, max_iter, int(backtracking), int(monotone), int(x0 is not None))
     info = RbpgInfo()
     lib().orc_rbpg(n, l, _ptr(A), _ptr(b), float(lam), float(Lf), ctypes.byref(o), _ptr(x),
                    ctypes.byref(info))
@@ -180,17 +182,20 @@ def _lam_array(lam, p):
 
 
 def rbpg_batch(A, B, lam, *, tol=1e-4, max_iter=500, c_alpha=0.5, alpha0=0.0,
-               backtracking=True, monotone=True, nthreads=0):
-    """Algorithm 1 (J = 1) on every pixel row of B; threads over pixels."""
+               backtracking=True, monotone=True, nthreads=0, X0=None):
+    """Algorithm 1 (J = 1) on every pixel row of B; threads over pixels.  X0
+    (P, L): the initial points x^(0) (default 0)."""
     A, B = _c128(A), _c128(B)
     n, l = A.shape
     p = B.shape[0]
     lam, stride = _lam_array(lam, p)
-    X = np.zeros((p, l), np.complex128)
+    X = np.zeros((p, l), np.complex128) if X0 is None else np.ascontiguousarray(_c128(X0)).copy()
+    if X.shape != (p, l):
+        raise ValueError("X0 must be (P, L)")
     iters = np.zeros(p, np.int32)
     kkt = np.zeros(p, np.float64)
     conv = np.zeros(p, np.int32)
-    o = RbpgOpts(alpha0, c_alpha, tol, max_iter, int(backtracking), int(monotone))
+    o = RbpgOpts(alpha0, c_alpha, tol, max_iter, int(backtracking), int(monotone), int(X0 is not None))
     lib().orc_rbpg_batch(n, l, p, _ptr(A), _ptr(B), _ptr(lam), stride, ctypes.byref(o),
                          int(nthreads), _ptr(X), _ptr(iters), _ptr(kkt), _ptr(conv))
     return X, {"iters": iters, "kkt_nat": kkt, "converged": conv.astype(bool)}

@@ -219,8 +219,16 @@ void orc_rbpg(int n, int l, const ocplx *A, const ocplx *b, double lambda, doubl
     double alpha_floor = 1.0 / Lf;
     if (opt->backtracking && alpha < alpha_floor) alpha = alpha_floor;
 
-    memset(x, 0, sizeof(ocplx) * l); /* Init: x^(0) = y^(0) = 0 */
-    double Fx = sqnorm(n, b);        /* F(0) = ||b||^2 */
+    double Fx;
+    if (opt->warm_start) {
+        /* Init: the given x^(0); x^(1) = x^(0), so the first step is a plain
+         * backtracked proximal-gradient step from it */
+        memcpy(xprev, x, sizeof(ocplx) * l);
+        Fx = orc_objective(n, l, A, b, lambda, x);
+    } else {
+        memset(x, 0, sizeof(ocplx) * l); /* Init: x^(0) = y^(0) = 0 */
+        Fx = sqnorm(n, b);               /* F(0) = ||b||^2 */
+    }
     int k = 0, backtracks = 0;
     double kkt = orc_kkt_nat(n, l, A, b, lambda, Lf, x);
     int done = kkt <= opt->tol;

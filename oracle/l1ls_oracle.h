@@ -69,6 +69,7 @@ typedef struct {
     int    max_iter; /* N_K                                                         */
     int    backtracking; /* 0: fixed step alpha0                                    */
     int    monotone;     /* 1: accept x-bar only if F(x-bar) <= F(x^k)               */
+    int    warm_start;   /* 1: x holds the initial point x^(0) on entry (orc_rbpg)   */
 } orc_rbpg_opts;
 
 typedef struct {
@@ -80,7 +81,9 @@ typedef struct {
     int    converged;   /* 1 if kkt_nat <= tol                                        */
 } orc_rbpg_info;
 
-/* Algorithm 1 with one block, FP64.  x (length L) is the output; starts at 0. */
+/* Algorithm 1 with one block, FP64.  x (length L) is the output; it starts at
+ * x^(0) = 0, or with opt->warm_start at the x^(0) that x holds on entry (the
+ * algorithm's initial point is an input).  x^(1) = x^(0) either way. */
 void orc_rbpg(int n, int l, const ocplx *A, const ocplx *b, double lambda, double Lf,
               const orc_rbpg_opts *opt, ocplx *x, orc_rbpg_info *info);
 

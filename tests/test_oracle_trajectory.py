@@ -97,3 +97,35 @@ def test_rbpg_golden_phase_equivariance(orc, phi):
         want = np.array([float(v) for v in r["x"]]) * rot
         assert np.allclose(x, want, rtol=1e-12, atol=1e-14), (r["k"], x, want)
         assert abs(info["objective"] - float(r["F"])) <= 1e-12 * float(r["F"])
+
+
+def warm_rows():
+    path = os.path.join(os.path.dirname(__file__), "golden", "algorithm1_warm_start.txt")
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, beta, alpha, shr, acc, x1, x2, F = line.split()
+        rows.append(dict(k=int(k), alpha=Fraction(alpha), x=(Fraction(x1), Fraction(x2)), F=Fraction(F)))
+    return rows
+
+
+def test_rbpg_warm_start_matches_golden(orc):
+    """Algorithm 1 from a given x^(0): the hand-derived first two iterates, steps and objectives
+    (tests/golden/algorithm1_warm_start.txt); from the minimiser it stops at once, unchanged."""
+    rows = warm_rows()
+    x0 = np.array([float(v) for v in rows[0]["x"]], dtype=np.complex128)
+    for r in rows[1:]:
+        x, info = orc.rbpg(A_G, B_G, LAM_G, tol=1e-300, max_iter=r["k"], Lf=LF_G, x0=x0)
+        assert np.allclose(x.real, [float(v) for v in r["x"]], rtol=1e-13, atol=1e-15), (r["k"], x)
+        assert np.abs(x.imag).max() == 0.0
+        assert abs(info["alpha"] - float(r["alpha"])) <= 1e-15
+        assert abs(info["objective"] - float(r["F"])) <= 1e-13 * float(r["F"])
+    xs = np.array([0.0, -14.0 / 5.0], dtype=np.complex128)
+    x, info = orc.rbpg(A_G, B_G, LAM_G, tol=1e-8, max_iter=50, Lf=LF_G, x0=xs)
+    assert info["iters"] == 0 and np.array_equal(x, xs)
+    # the batch form reads its X0 rows the same way
+    X, d = orc.rbpg_batch(A_G, np.stack([B_G, B_G]), LAM_G, tol=1e-300, max_iter=2,
+                          X0=np.stack([x0, x0]))
+    assert np.allclose(X.real, [[float(v) for v in rows[2]["x"]]] * 2, rtol=1e-13, atol=1e-15)
