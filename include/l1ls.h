@@ -138,13 +138,14 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
  * is created.  The stream must belong to the current device.
  *  - returns L1LS_ERR_WORKSPACE, with no work queued, when l1ls_workspace_size
  *    for (n, l, p) exceeds L1LS_NOALLOC_SCRATCH_BYTES (e.g. n = 25, l = 256
- *    holds about 150,000 pixels); split the pixels or call l1ls_solve.
+ *    holds about 240,000 pixels, n = 50, l = 512 about 88,000); split the
+ *    pixels or call l1ls_solve.
  *  - every call on one device shares that device's array, which keeps the last
  *    call's contents (the kernels clear what must start at zero): calls that
  *    overlap in time on one device race and give undefined results; serialise
  *    them (one stream, or events).
  *  - timing events (l1ls_timing_enable) are not recorded for these calls. */
-#define L1LS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+#define L1LS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 l1ls_status l1ls_solve_noalloc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
                                const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
                                l1ls_c32 *X, const l1ls_diag *diag, hipStream_t stream);
@@ -235,10 +236,12 @@ l1ls_status l1ls_unrolled_backward(int32_t n, int32_t l, int64_t p, const float 
  * A^H r (each 8 N L real flops), out[2] pixels handed to the FP64 refinement,
  * out[3] FP64 flops of the refinement's algorithm (full gradient passes
  * 8 N L each, working-set residuals and gradients 8 N |S|, Gram entries
- * 8 N, factorisations (2|S|)^3/3, substitutions 2 (2|S|)^2), counted by the
- * kernel as it runs.  `out` holds 4 entries. */
+ * 8 N, factorisations (2|S|)^3/3, substitutions 2 (2|S|)^2), out[4] the
+ * refinement's FP32 flops (its round-end gradient over all L bins, 8 N L a
+ * round, runs in FP32 under fp64_polish = 1), counted by the kernels as they
+ * run.  `out` holds 5 entries. */
 l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *workspace,
-                                hipStream_t stream, uint64_t out[4]);
+                                hipStream_t stream, uint64_t out[5]);
 
 /* Name of a status code; detail of the last error on the calling thread. */
 const char *l1ls_status_string(l1ls_status s);

@@ -34,7 +34,7 @@ EXPORTS = [
 KERNEL_ITERATION, KERNEL_REFINE, KERNEL_CERTIFY = 0, 1, 2
 
 # L1LS_NOALLOC_SCRATCH_BYTES: the fixed scratch of l1ls_solve_noalloc
-NOALLOC_SCRATCH_BYTES = 32 << 20
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Options(ctypes.Structure):
@@ -116,7 +116,7 @@ def load() -> ctypes.CDLL:
     L.l1ls_timing_read.restype = I32
     L.l1ls_timing_read_kernel.argtypes = [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
     L.l1ls_timing_read_kernel.restype = I32
-    L.l1ls_solve_counters.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(ctypes.c_uint64 * 4)]
+    L.l1ls_solve_counters.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(ctypes.c_uint64 * 5)]
     L.l1ls_solve_counters.restype = st
     _lib = L
     return L

@@ -147,12 +147,12 @@ def solve_noalloc(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor,
 
 
 def solve_counters(n: int, l: int, p: int, diag, stream=None):
-    """(forward products, adjoint products, pixels refined, refinement FP64 flops)
-    of the solve that made `diag`."""
-    out = (ctypes.c_uint64 * 4)()
+    """(forward products, adjoint products, pixels refined, refinement FP64 flops,
+    refinement FP32 flops) of the solve that made `diag`."""
+    out = (ctypes.c_uint64 * 5)()
     _lib.check(_lib.load().l1ls_solve_counters(n, l, p, _ptr(diag["_ws"]), _stream(stream),
                                                ctypes.byref(out)), "l1ls_solve_counters")
-    return int(out[0]), int(out[1]), int(out[2]), int(out[3])
+    return tuple(int(v) for v in out)
 
 
 def timing_enable(on: bool = True) -> None:

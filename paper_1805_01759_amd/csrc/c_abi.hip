@@ -67,6 +67,12 @@ StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
     off = align_up(off + (size_t)p * n * sizeof(float2), 256);
     w.overflow = off;
     off = align_up(off + (size_t)p * sizeof(int32_t), 256);
+    // the refinement's bin Gram A^H A and the A^H b of its workgroups' pixels
+    w.hgram = off;
+    off = align_up(off + (size_t)l * l * sizeof(double2), 256);
+    w.cbuf = off;
+    const int64_t groups = p < kMaxRefineGroups ? p : kMaxRefineGroups;
+    off = align_up(off + (size_t)groups * l * sizeof(double2), 256);
     w.total = off;
     return w;
 }
@@ -234,6 +240,8 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
 
     if (opt->fp64_polish) {
+        e = launch_setup_bin_gram(n, l, (const float2 *)A, (double2 *)(w + lay.hgram), s);
+        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "bin Gram launch: %s", hipGetErrorString(e));
         PolishArgsDev pa;
         pa.n = n;
         pa.l = l;
@@ -255,6 +263,9 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         pa.mode = opt->fp64_polish;
         pa.tol = opt->tol;
         pa.work = work;
+        pa.H = (const double2 *)(w + lay.hgram);
+        pa.cbuf = (double2 *)(w + lay.cbuf);
+        pa.max_groups = (int)(p < kMaxRefineGroups ? p : kMaxRefineGroups);
         int dev = 0, cus = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -433,11 +444,11 @@ const char *l1ls_status_string(l1ls_status s)
 const char *l1ls_last_error(void) { return g_err; }
 
 l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *workspace,
-                                hipStream_t stream, uint64_t out[4])
+                                hipStream_t stream, uint64_t out[5])
 {
     if (!workspace || !out) return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
     const StackWorkspace lay = stack_workspace_layout(n, l, p);
-    unsigned long long w2[3] = {0, 0, 0};
+    unsigned long long w2[4] = {0, 0, 0, 0};
     uint32_t q[4] = {0, 0, 0, 0};
     hipError_t e = hipMemcpyAsync(w2, (const char *)workspace + lay.work, sizeof w2,
                                   hipMemcpyDeviceToHost, stream);
@@ -450,6 +461,7 @@ l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *wor
     out[1] = w2[1];
     out[2] = q[1];
     out[3] = w2[2];
+    out[4] = w2[3];
     return L1LS_OK;
 }
 

@@ -125,6 +125,33 @@ __global__ void __launch_bounds__(256) setup_power_kernel(int n, int l, const fl
     }
 }
 
+// Bin Gram H = A^H A (FP64, l x l, row s holds H[s][m] = a_s^H a_m) for the
+// refinement's round-end gradient; one entry per thread, m the fast index.
+__global__ void __launch_bounds__(256) setup_bin_gram_kernel(int n, int l, const float2 *A, double2 *H)
+{
+    const int64_t total = (int64_t)l * l;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int sr = (int)(e / l), m = (int)(e % l);
+        double hr = 0.0, hi = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const float2 p = A[(size_t)i * l + sr], q = A[(size_t)i * l + m];
+            hr += (double)p.x * q.x + (double)p.y * q.y;  // conj(p) q
+            hi += (double)p.x * q.y - (double)p.y * q.x;
+        }
+        H[e] = make_double2(hr, hi);
+    }
+}
+
+hipError_t launch_setup_bin_gram(int n, int l, const float2 *A, double2 *H, hipStream_t s)
+{
+    const int64_t total = (int64_t)l * l;
+    int groups = (int)((total + 255) / 256);
+    if (groups > 4096) groups = 4096;
+    hipLaunchKernelGGL(setup_bin_gram_kernel, dim3(groups), dim3(256), 0, s, n, l, A, H);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 
 size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds)

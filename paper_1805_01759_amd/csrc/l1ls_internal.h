@@ -41,7 +41,8 @@ struct FistaArgs {
     const StackConsts *consts;
     uint32_t *queue;          // [0] next pixel
     uint32_t *polish_count;   // number of pixels appended to polish_list
-    unsigned long long *work; // [0] pixel forward products, [1] pixel adjoint products, [2] refinement flops
+    unsigned long long *work; // [0] pixel forward products, [1] pixel adjoint products,
+                              // [2] refinement FP64 flops, [3] refinement FP32 flops
     int32_t *polish_list;
     float2 *R;                // p x n: residual A x - b of the returned x (FP32), or null
     int32_t fista_cap;        // retire unsolved pixels after this many iterations
@@ -101,16 +102,23 @@ struct PolishArgsDev {
     int32_t *overflow;        // pixels left unsolved on a full working set (or null)
     uint32_t *overflow_count;
     uint32_t *status;         // workspace status: POLISHED is or-ed in
-    unsigned long long *work; // [2] accumulates the refinement's FP64 flops
+    unsigned long long *work; // [2] accumulates the refinement's FP64 flops, [3] its FP32 flops
+    const double2 *H;         // l x l bin Gram A^H A (FP64), H[s l + m] = a_s^H a_m
+    double2 *cbuf;            // kMaxRefineGroups x l: A^H b of each workgroup's pixel (FP64)
     int32_t rounds;
     int32_t mode;             // 1: refine pixels whose FP64 KKT > tol; 2: refine all
     float tol;
+    int32_t max_groups;       // workgroups the launch may use (<= kMaxRefineGroups)
 };
+
+// The refinement launches at most this many workgroups (12 per CU on 256 CUs):
+// each holds A^H b of its current pixel in the workspace.
+constexpr int kMaxRefineGroups = 3072;
 
 // Workspace layout for one stack.
 struct StackWorkspace {
     size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid,
-        overflow, total;
+        overflow, hgram, cbuf, total;
 };
 StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
 
@@ -123,6 +131,7 @@ int rows_pad_for(int n);       // rows of the packed A: N rounded up to 16
 hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, float2 *At, double2 *gram,
                         StackConsts *consts, uint32_t *queue, unsigned long long *work,
                         hipStream_t s);
+hipError_t launch_setup_bin_gram(int n, int l, const float2 *A, double2 *H, hipStream_t s);
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s,
                         bool *keeps_residual = nullptr);
 hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s);

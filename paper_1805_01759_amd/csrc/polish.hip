@@ -59,7 +59,7 @@ __device__ __forceinline__ float lane_value_f(float v, int i)
 #endif
 constexpr int kMaxSupp = L1LS_POLISH_SUPP;
 static_assert(kMaxSupp == 16 || kMaxSupp == 32, "working sets of 16 or 32 slots");
-// violators admitted per round: the wide pass grows its set by up to 4 a round
+// violators admitted per round: the wide pass grows its set by up to 8 a round
 // (the next-largest violations of distinct lanes), the first pass by one
 constexpr int kEnter = kMaxSupp == 32 ? 8 : 1;
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
@@ -173,6 +173,10 @@ __device__ double phi_support(const PolishArgsDev &a, PolishShared &sh, float2 b
 // starting point against tol itself stays FP64.
 // Magnitudes are compared squared; the prox scale (a square root and a
 // division) is formed only on lanes whose |v| passes the threshold.
+template <bool START>
+__device__ void pass_finish(PolishShared &sh, double acc, double l1, double km, double vbest,
+                            double lam, double lf, double &F, double &kk, int &vidx);
+
 template <bool START, bool F32>
 __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2 *x0, int s, int nnz,
                           double lam, double lf, double inv_lf, double &F, double &kk, int &vidx)
@@ -270,6 +274,16 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2
             }
         }
     }
+    pass_finish<START>(sh, acc, l1, km, vbest, lam, lf, F, kk, vidx);
+}
+
+// Reductions that end a pass: the objective, the natural KKT residual and the
+// violators (the worst one in vidx; with kEnter > 1 the list sh.vl / sh.nv).
+template <bool START>
+__device__ void pass_finish(PolishShared &sh, double acc, double l1, double km, double vbest,
+                            double lam, double lf, double &F, double &kk, int &vidx)
+{
+    const int lane = threadIdx.x;
     F = wsum(acc + lam * l1);
     kk = sqrt(wmax(km)) * lf / lam;
     if constexpr (kEnter > 1) {
@@ -306,6 +320,101 @@ __device__ void full_pass(const PolishArgsDev &a, PolishShared &sh, const float2
         if (best < 0 || m < best) best = m;
     }
     vidx = best;
+}
+
+// c = A^H b of the pixel in FP64 into the workgroup's buffer `cb` (lane m
+// writes and later reads its own bins m = lane + 64 k); b is staged in sh.w.
+__device__ void bin_rhs(const PolishArgsDev &a, PolishShared &sh, float2 b0, float2 b1, double2 *cb)
+{
+    const int lane = threadIdx.x;
+    if (lane < a.n) sh.w[lane] = make_double2(b0.x, b0.y);
+    if (lane + 64 < a.n) sh.w[lane + 64] = make_double2(b1.x, b1.y);
+    __syncthreads();
+    for (int m = lane; m < a.l; m += 64) {
+        double cr = 0.0, ci = 0.0;
+        int nn = 0;
+        for (; nn + 8 <= a.n; nn += 8) {
+            float2 af[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) af[u] = a.A[(unsigned)((nn + u) * a.l_pad + m)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double2 bv = sh.w[nn + u];
+                cr += (double)af[u].x * bv.x + (double)af[u].y * bv.y;  // conj(a) b
+                ci += (double)af[u].x * bv.y - (double)af[u].y * bv.x;
+            }
+        }
+        for (; nn < a.n; ++nn) {
+            const float2 af = a.A[(unsigned)(nn * a.l_pad + m)];
+            const double2 bv = sh.w[nn];
+            cr += (double)af.x * bv.x + (double)af.y * bv.y;
+            ci += (double)af.x * bv.y - (double)af.y * bv.x;
+        }
+        cb[m] = make_double2(cr, ci);
+    }
+    __syncthreads();
+}
+
+// The round-end pass in Gram form: g_m / 2 = sum_t H[m][S_t] z_t - c_m with
+// H = A^H A (FP64; H[m][s] = conj(H[s][m]), row S_t read contiguously) and
+// c = A^H b from bin_rhs, then the same natural KKT residual, objective (from
+// the exact residual sh.r) and violators as full_pass.  It reads 16 (|S| + 1)
+// bytes a bin where the residual form reads a column of A (8 N bytes), so it
+// is the cheaper one while 2 (|S| + 1) <= N; everything stays FP64.
+__device__ void gram_pass(const PolishArgsDev &a, PolishShared &sh, const double2 *cb, int s,
+                          double lam, double lf, double inv_lf, double &F, double &kk, int &vidx)
+{
+    const int lane = threadIdx.x;
+    double acc = 0.0, l1 = 0.0, km = 0.0, vbest = 0.0;
+    vidx = -1;
+    for (int nn = lane; nn < a.n; nn += 64) {
+        const double2 rv = sh.r[nn];
+        acc += rv.x * rv.x + rv.y * rv.y;
+    }
+    for (int t = lane; t < s; t += 64) l1 += sqrt(sh.z[t].x * sh.z[t].x + sh.z[t].y * sh.z[t].y);
+    const double tau = lam * inv_lf, tau2 = tau * tau;
+    const double lv = lam * (1.0 + 1e-12), lv2 = lv * lv;
+    for (int m = lane; m < a.l; m += 64) {
+        const double2 cm = cb[m];
+        double gr = -cm.x, gi = -cm.y;
+        int t = 0;
+        for (; t + 4 <= s; t += 4) {
+            double2 hv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) hv[u] = a.H[(size_t)sh.S[t + u] * a.l + m];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double2 zv = sh.z[t + u];
+                gr += hv[u].x * zv.x + hv[u].y * zv.y;  // conj(H[S_t][m]) z_t
+                gi += hv[u].x * zv.y - hv[u].y * zv.x;
+            }
+        }
+        for (; t < s; ++t) {
+            const double2 hv = a.H[(size_t)sh.S[t] * a.l + m];
+            const double2 zv = sh.z[t];
+            gr += hv.x * zv.x + hv.y * zv.y;
+            gi += hv.x * zv.y - hv.y * zv.x;
+        }
+        const int ts = sh.sidx[m];
+        const double2 v = ts >= 0 ? sh.z[ts] : make_double2(0.0, 0.0);
+        const double xr = v.x, xi = v.y;
+        const double g_r = 2.0 * gr, g_i = 2.0 * gi;
+        const double vr = xr - g_r * inv_lf, vi = xi - g_i * inv_lf;
+        const double m2 = vr * vr + vi * vi;
+        double er = xr, ei = xi;  // x - prox(v), prox(v) = 0 when |v| <= tau
+        if (m2 > tau2) {
+            const double sc = 1.0 - tau / sqrt(m2);
+            er = xr - vr * sc;
+            ei = xi - vi * sc;
+        }
+        km = fmax(km, er * er + ei * ei);
+        const double gm2 = g_r * g_r + g_i * g_i;
+        if (xr == 0.0 && xi == 0.0 && gm2 > lv2 && gm2 > vbest) {
+            vbest = gm2;
+            vidx = m;
+        }
+    }
+    pass_finish<false>(sh, acc, l1, km, vbest, lam, lf, F, kk, vidx);
 }
 
 // Gram entries G_tu = a_t^H a_u (t >= u) for the packed indices [e0, e1) into
@@ -548,8 +657,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
     const double gstop = a.mode == 2 ? 1e-13 : 1e-2 * (double)a.tol;
     const double kstop = a.mode == 2 ? 1e-10 : 1e-1 * (double)a.tol;
     const uint32_t count = *a.count;
-    // FP64 flops of the algorithm (wave-uniform): 8 per complex multiply-add
-    unsigned long long fl = 0;
+    double2 *cb = a.cbuf + (size_t)blockIdx.x * a.l;  // A^H b of this workgroup's pixel
+    bool have_c = false;
+    // flops of the algorithm (wave-uniform), 8 per complex multiply-add: FP64
+    // work in fl, the FP32 round-end gradient of mode 1 in fl32
+    unsigned long long fl = 0, fl32 = 0;
     const unsigned long long f8n = 8ull * (unsigned long long)a.n;
     // pixels are taken from a shared counter, so a workgroup that becomes
     // resident late only finds what is left
@@ -611,6 +723,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             __syncthreads();
             if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
         }
+        have_c = false;
         // -- working set: the local maxima of |x| (FISTA spreads one scatterer
         //    over neighbouring bins); at most kMaxSupp, the largest kept
         if (lane == 0) sh.cnt = 0;
@@ -907,11 +1020,24 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
             if (fresh) phi_support(a, sh, b0, b1, sh.z, s, lam);  // r only: c is formed afresh next round
             double F, kk;
             int vidx;
-            if (a.mode == 1)
+            if (round > 0 && 2 * (s + 1) <= a.n) {
+                // Gram form (FP64): |S| rows of A^H A and A^H b instead of a column of A a bin
+                // (from the second round on: A^H b costs one pass of its own)
+                if (!have_c) {
+                    bin_rhs(a, sh, b0, b1, cb);
+                    fl += f8n * (unsigned long long)a.l;
+                    have_c = true;
+                }
+                gram_pass(a, sh, cb, s, lam, lf, inv_lf, F, kk, vidx);
+                fl += f8n * (unsigned long long)s + 8ull * (unsigned long long)a.l * (unsigned long long)s;
+            } else if (a.mode == 1) {
                 full_pass<false, true>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
-            else
+                fl += f8n * (unsigned long long)s;
+                fl32 += f8n * (unsigned long long)a.l;
+            } else {
                 full_pass<false, false>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
-            fl += f8n * (unsigned long long)(s + a.l);
+                fl += f8n * (unsigned long long)(s + a.l);
+            }
             if (F <= fbest) {
                 fbest = F;
                 if (lane < s) {
@@ -1005,6 +1131,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
         __syncthreads();
     }
     if (lane == 0 && fl) atomicAdd(&a.work[2], fl);
+    if (lane == 0 && fl32) atomicAdd(&a.work[3], fl32);
 }
 
 size_t polish_lds_bytes(int n, int l_pad)
@@ -1023,7 +1150,9 @@ hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s)
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int g = per_cu > 0 ? per_cu * cus : groups;
+    int g = per_cu > 0 ? per_cu * cus : groups;
+    if (g > a.max_groups) g = a.max_groups;  // one A^H b buffer per workgroup
+    if (g < 1) g = 1;
     hipLaunchKernelGGL(polish_kernel, dim3(g), dim3(64), dyn, s, a);
     return hipGetLastError();
 }
