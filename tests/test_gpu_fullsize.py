@@ -33,13 +33,16 @@ def _rel_err(X, Xe, B, Lf):
     return np.linalg.norm(X - Xe, axis=1) / den
 
 
-def _check_sampled(orc, A32, B32, l32, X, d, idx, bar, min_solved=0.9999, median_e=1e-5):
+def _check_sampled(orc, A32, B32, l32, X, d, idx, bar, min_solved=0.9999, median_e=1e-5,
+                   pass_floor=None):
     """What is unique in the result is checked exactly: the certified KKT residual
     of the returned x (device vs oracle) and its objective against the minimiser's
-    (relative gap within bar, never below the minimum beyond rounding).  x itself
-    is any point with KKT <= tol; its distance to the minimiser is reported (for
-    near-adjacent bins the minimiser is ill-conditioned, so a small KKT residual
-    does not bound it)."""
+    (relative gap within bar, never below the minimum beyond rounding).  The
+    distance to the minimiser, e_p = ||x - x*|| / max(||x*||, ||b|| / sigma_max),
+    is reported and its pass fraction (e_p <= bar and solved) held to
+    `pass_floor`: for near-adjacent bins the minimiser is ill-conditioned, so a
+    KKT residual at tol does not bound e_p; the solves here refine every pixel to
+    FP64 accuracy (the benchmark's mode), which does for all but a few pixels."""
     A64 = A32.astype(np.complex128)
     Lf = orc.lipschitz(A64)
     Bs = B32[idx].astype(np.complex128)
@@ -55,39 +58,46 @@ def _check_sampled(orc, A32, B32, l32, X, d, idx, bar, min_solved=0.9999, median
     e = _rel_err(Xg, Xe, Bs, Lf)
     st = d["status"].cpu().numpy()
     conv = (st & _lib.PX_CONVERGED) != 0
+    passed = conv[idx] & (e <= bar)
     print(f"solved {conv.mean():.6f}; sampled objective gap max {gap.max():.1e}; kkt max {ko.max():.1e}; "
-          f"x vs minimiser: e p50 {np.median(e):.1e}, > 1e-4 {np.mean(e > 1e-4):.3f}, max {e.max():.1e}")
+          f"x vs minimiser: e p50 {np.median(e):.1e}, p99 {np.percentile(e, 99):.1e}, max {e.max():.1e}; "
+          f"parity pass {passed.mean():.4f} at bar {bar:g}")
     assert conv.mean() >= min_solved
     assert np.allclose(kg, ko, rtol=1e-5, atol=1e-9)
     assert (ko[conv[idx]] <= 1e-4 * (1 + 1e-5)).all()
     assert gap.min() >= -1e-12 and gap.max() <= bar
     if median_e is not None:
         assert np.median(e) <= median_e
+    if pass_floor is not None:
+        assert passed.mean() >= pass_floor
+    return e, passed
 
 
-@pytest.mark.parametrize("prec,bar", [("fp32", 1e-4), ("split_bf16", 1e-3)])
-def test_scene_full_size(dev, orc, prec, bar):
+# pass-fraction floors of e_p <= bar (and solved) on the sampled pixels, in the
+# benchmark's configuration; measured: scene 0.98 / 0.99, close pairs 0.98 / 0.996
+@pytest.mark.parametrize("prec,bar,floor", [("fp32", 1e-4, 0.95), ("split_bf16", 1e-3, 0.95)])
+def test_scene_full_size(dev, orc, prec, bar, floor):
     spec, geom, B, lam = synth.make_config(2)
     A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
     Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
-    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, precision=prec, fp64_polish=1,
+    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, precision=prec, fp64_polish=bench.ACCURACY_MODE,
                      polish_after=bench.POLISH_AFTER)
     p = B32.shape[0]
     idx = np.arange(7, p, p // 256)
-    _check_sampled(orc, A32, B32, l32, X, d, idx, bar)
+    _check_sampled(orc, A32, B32, l32, X, d, idx, bar, pass_floor=floor)
 
 
-@pytest.mark.parametrize("prec,bar", [("fp32", 1e-4), ("split_bf16", 1e-3)])
-def test_close_pairs_full_size(dev, orc, prec, bar):
+@pytest.mark.parametrize("prec,bar,floor", [("fp32", 1e-4, 0.95), ("split_bf16", 1e-3, 0.95)])
+def test_close_pairs_full_size(dev, orc, prec, bar, floor):
     spec, geom, B, lam = synth.make_config(4)
     A32, B32, l32 = synth.to_device_dtypes(geom.A, B, lam)
     del B
     Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
-    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, precision=prec, fp64_polish=1,
+    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, precision=prec, fp64_polish=bench.ACCURACY_MODE,
                      polish_after=bench.POLISH_AFTER)
     p = B32.shape[0]
-    idx = np.arange(11, p, p // 96)
-    _check_sampled(orc, A32, B32, l32, X, d, idx, bar)
+    idx = np.arange(11, p, p // 192)
+    _check_sampled(orc, A32, B32, l32, X, d, idx, bar, pass_floor=floor)
 
 
 def test_batched_full_size(dev, orc):
@@ -102,17 +112,23 @@ def test_batched_full_size(dev, orc):
                        "X": torch.empty((ss.p, ss.l), dtype=torch.complex64, device=dev),
                        "diag": api.new_diag(ss.p, dev)})
     plan = api.Plan([(ss.n, ss.l, ss.p) for ss in specs], max_iter=500, tol=1e-4,
-                    fp64_polish=1, polish_after=bench.POLISH_AFTER)
+                    fp64_polish=bench.ACCURACY_MODE, polish_after=bench.POLISH_AFTER)
     ws = torch.empty(plan.workspace_bytes + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
     plan.execute(stacks, ws[off:off + plan.workspace_bytes])
     torch.cuda.synchronize()
+    all_pass = []
     for (A32, B32, l32), st in zip(host, stacks):
         p = B32.shape[0]
         idx = np.unique(np.array([0, p // 3, (2 * p) // 3, p - 1]))
         # grids of up to 1024 bins over 100 m: the minimiser's distance is not
         # bounded by the certificate (reported, not asserted)
-        _check_sampled(orc, A32, B32, l32, st["X"], st["diag"], idx, 1e-4, min_solved=0.999, median_e=None)
+        _, passed = _check_sampled(orc, A32, B32, l32, st["X"], st["diag"], idx, 1e-4, min_solved=0.999,
+                                   median_e=None)
+        all_pass.append(passed)
+    passed = np.concatenate(all_pass)
+    print(f"batched: parity pass over {len(passed)} sampled pixels of 64 stacks: {passed.mean():.4f}")
+    assert passed.mean() >= 0.9
 
 
 def test_unrolled_full_size(dev, orc):

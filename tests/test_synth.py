@@ -100,3 +100,35 @@ def test_motion_pixels_follow_the_model():
     assert abs(np.mean(ratio) - 1.0) < 0.02
     frac = np.bincount(meta["k"], minlength=3) / 8000
     assert np.allclose(frac, [0.3, 0.5, 0.2], atol=0.02)
+
+
+def test_superres_cases():
+    """Double-scatterer stacks: N = 29 over the full 269.5 m aperture, rho_s from it,
+    the pair at +-kappa rho_s / 2, unit amplitudes, phase difference 0 in the
+    detection set, noise at the per-scatterer SNR, ranges regenerate alone."""
+    R = 400
+    geom, B, lam, meta = synth.make_superres(R)
+    ncase = len(synth.SUPERRES_CASES)
+    assert B.shape == (ncase * R, 29) and geom.A.shape == (29, 256)
+    assert math.isclose(geom.baselines.max() - geom.baselines.min(), 269.5)
+    assert math.isclose(geom.rayleigh, 0.031 * 7e5 / (2 * 269.5))
+    for c, (kind, kappa, snr) in enumerate(synth.SUPERRES_CASES):
+        sl = slice(c * R, (c + 1) * R)
+        assert np.all(meta["case"][sl] == c) and np.all(meta["kappa"][sl] == kappa)
+        assert np.allclose(meta["s2"][sl] - meta["s1"][sl], kappa * geom.rayleigh)
+        assert np.allclose(meta["s1"][sl] + meta["s2"][sl], 0.0)
+        a1 = synth.steering(geom.xi, meta["s1"][sl][:1])[0]
+        a2 = synth.steering(geom.xi, meta["s2"][sl][:1])[0]
+        sig = a1[None, :] + np.exp(1j * meta["dphi"][sl])[:, None] * a2[None, :]
+        noise = B[sl] - sig
+        sigma2 = 10 ** (-snr / 10)
+        assert abs((np.abs(noise) ** 2).mean() / sigma2 - 1) < 0.05
+        assert np.allclose(lam[sl], math.sqrt(sigma2) * math.sqrt(2 * 29 * math.log(256)))
+        if kind == "detection":
+            assert np.all(meta["dphi"][sl] == 0.0)
+        else:
+            assert meta["dphi"][sl].min() >= 0 and meta["dphi"][sl].max() < 2 * math.pi
+            assert meta["dphi"][sl].std() > 1.5
+    _, B2, _, meta2 = synth.make_superres(100, r0=250)
+    for c in range(ncase):
+        assert np.array_equal(B2[c * 100:(c + 1) * 100], B[c * R + 250:c * R + 350])
