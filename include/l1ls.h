@@ -86,7 +86,11 @@ typedef struct {
                               minimiser has more nonzeros is returned unsolved (status bits) */
     int32_t polish_after;  /* hand a pixel to the refinement after this many iterations
                               (<= max_iter; <= 0 means max_iter)                              */
-    int32_t warm_start;    /* reserved, must be 0                                              */
+    int32_t warm_start;    /* 0: Algorithm 1 starts at x^(0) = 0; 1: X holds each pixel's
+                              initial point x^(0) on entry (the Init of Algorithm 1; x^(1) =
+                              x^(0), the step starts at alpha_0).  Not available in
+                              l1ls_solve_blocks or with split-BF16 for l > 256
+                              (L1LS_ERR_UNSUPPORTED_SHAPE)                                   */
 } l1ls_options;
 
 /* Device arrays of length P; any may be NULL.
@@ -118,7 +122,8 @@ l1ls_status l1ls_workspace_size(int32_t n, int32_t l, int64_t p, const l1ls_opti
  *  B        device, p*n, pixel-major measurement vectors g_p of Eq. (5)
  *  lambda   device float; lambda_stride 0 = one value for all pixels, else
  *           lambda[p * lambda_stride]
- *  X        device, p*l: output (the pixel's x)
+ *  X        device, p*l: output (the pixel's x); with opt->warm_start also the
+ *           input (each pixel's initial point), overwritten by the result
  *  diag     host struct of device pointers (may be NULL)
  *  workspace/ws_bytes  device scratch of at least l1ls_workspace_size bytes,
  *           16-byte aligned; its contents on entry are ignored

@@ -23,7 +23,7 @@ def _stream(stream=None):
 
 
 def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracking=True,
-            monotone=True, fp64_polish=1, polish_after=0) -> _lib.Options:
+            monotone=True, fp64_polish=1, polish_after=0, warm_start=False) -> _lib.Options:
     o = _lib.load().l1ls_options_default()
     o.max_iter = int(max_iter)
     o.tol = float(tol)
@@ -33,6 +33,7 @@ def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracki
     o.monotone = int(bool(monotone))
     o.fp64_polish = int(fp64_polish)  # 0 off, 1 pixels above tol, 2 every pixel
     o.polish_after = int(polish_after)
+    o.warm_start = int(bool(warm_start))  # X (out) holds the initial points on entry
     return o
 
 
@@ -89,6 +90,8 @@ def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = N
           draws: torch.Tensor | None = None, **opts):
     """Solve min ||A x - b_p||^2 + lambda_p ||x||_1 for every row b_p of B.
 
+    With warm_start=True, `out` must hold each pixel's initial point x^(0) of
+    Algorithm 1 on entry (it is overwritten by the result).
     Returns (X, diag) with X (P, L) complex64 and diag a dict of device tensors
     (iters int32, kkt float32, objective float32, status int32 bits, nnz int32).
     blocks > 0: Algorithm 1 with that many column blocks (l1ls_solve_blocks),
@@ -99,6 +102,8 @@ def solve(A: torch.Tensor, B: torch.Tensor, lam, *, out: torch.Tensor | None = N
     n, l = A.shape
     p = B.shape[0]
     o = options(**opts)
+    if o.warm_start and out is None:
+        raise ValueError("warm_start needs `out` holding the initial points")
     X = out if out is not None else torch.empty((p, l), dtype=torch.complex64, device=B.device)
     diag = {
         "iters": torch.empty(p, dtype=torch.int32, device=B.device),

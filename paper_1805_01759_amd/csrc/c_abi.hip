@@ -103,7 +103,7 @@ static l1ls_status check_options(const l1ls_options *o)
         return fail(L1LS_ERR_INVALID_ARG, "c_alpha must lie in (0, 1)");
     if (o->precision != L1LS_FP32 && o->precision != L1LS_SPLIT_BF16)
         return fail(L1LS_ERR_INVALID_ARG, "unknown precision %d", o->precision);
-    if (o->warm_start != 0) return fail(L1LS_ERR_INVALID_ARG, "warm_start is not supported");
+    if (o->warm_start != 0 && o->warm_start != 1) return fail(L1LS_ERR_INVALID_ARG, "warm_start must be 0 or 1");
     if (o->fp64_polish < 0 || o->fp64_polish > 2)
         return fail(L1LS_ERR_INVALID_ARG, "fp64_polish must be 0, 1 or 2");
     return L1LS_OK;
@@ -173,6 +173,20 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
 
     char *w = (char *)ws;
     const int waves = waves_for(l), l_pad = lpad_for(l);
+    if (opt->warm_start) {
+        // Algorithm 1 from X runs in the split re/im MFMA kernels and the wave kernel
+        if (choice == kBlocks)
+            return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "warm_start is not available in the block form");
+        FistaArgs probe{};
+        probe.n = n;
+        probe.l = l;
+        probe.l_pad = l_pad;
+        probe.waves = waves;
+        const int ch = choice == kAuto ? (mfma_supports(n, l) ? kMfma : kWave) : choice;
+        if (ch == kMfma && !fista_split_kernel(probe, opt->precision))
+            return fail(L1LS_ERR_UNSUPPORTED_SHAPE,
+                        "warm_start with split-BF16 needs l <= 256 (n = %d, l = %d)", n, l);
+    }
     float2 *Ap = (float2 *)(w + lay.a_packed);
     double2 *gram = (double2 *)(w + lay.gram);
     StackConsts *consts = (StackConsts *)(w + lay.consts);
@@ -216,6 +230,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     fa.backtracking = opt->backtracking ? 1 : 0;
     fa.monotone = opt->monotone ? 1 : 0;
     fa.polish = opt->fp64_polish;
+    fa.warm = opt->warm_start;
     if (choice == kBlocks) {
         BlocksArgs ba;
         ba.f = fa;

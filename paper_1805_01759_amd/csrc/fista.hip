@@ -257,8 +257,18 @@ static hipError_t launch_mfma_t(const FistaArgs &a, int max_groups, hipStream_t 
                : launch_mfma_one<T, 8, false, L1LS_FP32, 4>(a, max_groups, s);
 }
 
+// Whether launch_fista runs a split re/im kernel (fista_mfma.h) for this shape
+// and precision; the real-embedded kernels (fista_impl.h) have no warm start.
+bool fista_split_kernel(const FistaArgs &a, int precision)
+{
+    const int T = rows_pad_for(a.n) / 16;
+    if (precision == L1LS_SPLIT_BF16) return slice_blocks_for(a.l) == 8 && mfma_lds_fits(a, L1LS_SPLIT_BF16) && T <= 4;
+    return T <= 4;
+}
+
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s, bool *keeps_residual)
 {
+    if (a.warm && !fista_split_kernel(a, precision)) return hipErrorNotSupported;
     const int T = rows_pad_for(a.n) / 16;
     // the split re/im kernels (fista_mfma.h) write a.R; the real-embedded ones do not
     if (keeps_residual)

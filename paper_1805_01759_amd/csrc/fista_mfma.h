@@ -249,15 +249,18 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
     // the retiring slots are known so that its latency hides under the acceptance
     // (the barrier that publishes it is the only one here: the next write of sQ
     // comes after the next trial's barriers).
+    unsigned long long n_fwd = 0, n_adj = 0;  // pixel products (thread 0 counts)
     auto refill = [&](uint32_t mask, uint32_t got) {
         if (mask == 0) return;
         const bool mine = (mask >> j) & 1u;
         bool fresh = false;
+        bool any_fresh = false;  // workgroup-uniform
         if (!qdone) {
             const uint32_t nfree = __popc(mask);
             if (tid == 0) sQ[0] = got;
             __syncthreads();
             const uint64_t base = sQ[0];
+            any_fresh = base < (uint64_t)a.p;
             if (base + nfree >= (uint64_t)a.p) qdone = true;
             const uint64_t np = base + (uint64_t)__popc(mask & ((1u << j) - 1u));
             fresh = mine && np < (uint64_t)a.p;
@@ -302,6 +305,98 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
             }
         bb = fm::sum_h(bb);
         if (fresh) Fk = bb;
+        if (a.warm && any_fresh) {
+            // Init of Algorithm 1 from the given x^(0) (in X) for the fresh slots:
+            // x^1 = x^0, r_1 = A x^0 - b (one FP32 product from the packed A in
+            // global memory, for either precision) and F(x^0) = ||r_1||^2 + lambda ||x^0||_1
+            const float2 *Xi0 = a.X + (size_t)(fresh ? pix : 0) * l;
+            float l1p = 0.0f;
+#pragma unroll
+            for (int b = 0; b < KB; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = m_base + 16 * b + 4 * h + q;
+                    const float2 v = fresh && m < l ? Xi0[m] : make_float2(0.0f, 0.0f);
+                    Xr[b][q] = fresh ? v.x : Xr[b][q];
+                    Xi[b][q] = fresh ? v.y : Xi[b][q];
+                    Xpr[b][q] = Xr[b][q];
+                    Xpi[b][q] = Xi[b][q];
+                    l1p += fresh ? __builtin_amdgcn_sqrtf(fmaf(v.x, v.x, v.y * v.y)) : 0.0f;
+                }
+            const fm::AView Ag{a.A, a.l_pad};
+            f4 Vr[T], Vi[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) Vr[t] = Vi[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                const int m0 = m_base + 16 * b + 4 * h;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const f4 a01 = Ag.load4(16 * t + j, m0), a23 = Ag.load4(16 * t + j, m0 + 2);
+                    // W_re += A_re x_re - A_im x_im;  W_im += A_im x_re + A_re x_im
+                    Vr[t] = fm::mfma(a01[0], Xr[b][0], Vr[t]);
+                    Vr[t] = fm::mfma(a01[1], -Xi[b][0], Vr[t]);
+                    Vi[t] = fm::mfma(a01[1], Xr[b][0], Vi[t]);
+                    Vi[t] = fm::mfma(a01[0], Xi[b][0], Vi[t]);
+                    Vr[t] = fm::mfma(a01[2], Xr[b][1], Vr[t]);
+                    Vr[t] = fm::mfma(a01[3], -Xi[b][1], Vr[t]);
+                    Vi[t] = fm::mfma(a01[3], Xr[b][1], Vi[t]);
+                    Vi[t] = fm::mfma(a01[2], Xi[b][1], Vi[t]);
+                    Vr[t] = fm::mfma(a23[0], Xr[b][2], Vr[t]);
+                    Vr[t] = fm::mfma(a23[1], -Xi[b][2], Vr[t]);
+                    Vi[t] = fm::mfma(a23[1], Xr[b][2], Vi[t]);
+                    Vi[t] = fm::mfma(a23[0], Xi[b][2], Vi[t]);
+                    Vr[t] = fm::mfma(a23[2], Xr[b][3], Vr[t]);
+                    Vr[t] = fm::mfma(a23[3], -Xi[b][3], Vr[t]);
+                    Vi[t] = fm::mfma(a23[3], Xr[b][3], Vi[t]);
+                    Vi[t] = fm::mfma(a23[2], Xi[b][3], Vi[t]);
+                }
+            }
+            l1p = fm::sum_h(l1p);
+            // the same two-stage cross-wave sum as the trial's forward product
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                sPW[((size_t)w * 2 * T + 2 * t) * 64 + lane] = Vr[t];
+                sPW[((size_t)w * 2 * T + 2 * t + 1) * 64 + lane] = Vi[t];
+            }
+            if (h == 0) sPS[w * 16 + j] = f4{l1p, 0.0f, 0.0f, 0.0f};
+            __syncthreads();
+            {
+                const int EW = 2 * T * 64, E = EW + 16;
+                for (int e = tid; e < E; e += blockDim.x) {
+                    if (e < EW) {
+                        f4 acc = sPW[e];
+                        for (int ww = 1; ww < W; ++ww) acc += sPW[(size_t)ww * EW + e];
+                        sPW[e] = acc;
+                    } else {
+                        f4 acc = sPS[e - EW];
+                        for (int ww = 1; ww < W; ++ww) acc[0] += sPS[ww * 16 + e - EW][0];
+                        sPS[e - EW] = acc;
+                    }
+                }
+            }
+            __syncthreads();
+            float rr = 0.0f;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const f4 wr = sPW[(size_t)(2 * t) * 64 + lane], wi = sPW[(size_t)(2 * t + 1) * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // rows n >= N: A is zero there, and so is -b
+                    const float r_r = wr[q] + Rr[t][q], r_i = wi[q] + Ri[t][q];  // A x0 - b
+                    Rr[t][q] = fresh ? r_r : Rr[t][q];
+                    Ri[t][q] = fresh ? r_i : Ri[t][q];
+                    Rpr[t][q] = fresh ? r_r : Rpr[t][q];
+                    Rpi[t][q] = fresh ? r_i : Rpi[t][q];
+                    rr = fmaf(r_r, r_r, fmaf(r_i, r_i, rr));
+                }
+            }
+            rr = fm::sum_h(rr);
+            const float l1 = sPS[j][0];
+            __syncthreads();
+            if (fresh) Fk = fmaf(lam, l1, rr);
+            n_fwd += __popcll(__ballot(fresh && h == 0));
+        }
     };
 
     // ---- G = 2 A^H r for the wave's unknowns (all slots)
@@ -378,7 +473,6 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
         }
     };
 
-    unsigned long long n_fwd = 0, n_adj = 0;  // pixel products (thread 0 counts)
     uint32_t qgot = 0;                        // thread 0: queue position for the retiring slots
     refill(0xFFFFu, tid == 0 ? atomicAdd(a.queue, 16u) : 0u);
     if (__ballot(active) == 0) return;
@@ -584,8 +678,8 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
             l1 = S[1];
             float d2s = S[0];
             bool jumped = false;
-            if (k == 1 && trial == 0 && active && !retire && a.backtracking && w2 > d2s / (2.0f * alpha) &&
-                alpha > afloor) {
+            if (k == 1 && trial == 0 && !a.warm && active && !retire && a.backtracking &&
+                w2 > d2s / (2.0f * alpha) && alpha > afloor) {
                 // First iteration: y = x^0 = 0, so x-bar(alpha) = alpha S_lambda(-G_0) is linear
                 // in alpha and Eq. (15) reads alpha <= ||d||^2 / (2 ||A d||^2) at every alpha.
                 // The shrink sequence alpha0 C^i therefore ends where this one product

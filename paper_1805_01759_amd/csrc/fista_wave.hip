@@ -86,6 +86,33 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
         for (int c = 0; c < NC; ++c) G[c] = make_float2(2.0f * gr[c], 2.0f * gi[c]);
     };
 
+    // W = A D (D in LDS): lanes over rows (rpl lanes per row when N is small,
+    // each taking every rpl-th column), A read through its transposed copy so
+    // that the lanes' loads are contiguous; returns ||W||^2
+    auto forward = [&]() {
+        float w2 = 0.0f;
+        for (int i0 = 0; i0 < n; i0 += rows_per_pass) {
+            const int i = i0 + lane % rows_per_pass, part = lane / rows_per_pass;
+            float wr = 0.0f, wi = 0.0f;
+            if (i < n) {
+                for (int j = part; j < l; j += rpl) {
+                    const float2 av = a.At[(size_t)j * n + i], dv = D[j];
+                    wr = fmaf(av.x, dv.x, fmaf(-av.y, dv.y, wr));
+                    wi = fmaf(av.x, dv.y, fmaf(av.y, dv.x, wi));
+                }
+            }
+            for (int o = rows_per_pass; o < 64; o <<= 1) {
+                wr += __shfl_xor(wr, o, 64);
+                wi += __shfl_xor(wi, o, 64);
+            }
+            if (i < n && part == 0) {
+                W[i] = make_float2(wr, wi);
+                w2 += wr * wr + wi * wi;
+            }
+        }
+        return wsumf(w2);
+    };
+
     for (;;) {
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(a.queue, 1u);
@@ -96,15 +123,42 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
         const bool bad = !(lam > 0.0f) || !isfinite(lam);
         if (bad) lam = 1.0f;
         const float2 *b = a.B + (size_t)pix * n;
+        float Fk;
+        if (a.warm) {
+            // Init of Algorithm 1 from the given x^(0) (in X): x^1 = x^0,
+            // r_1 = A x^0 - b and F(x^0) = ||r_1||^2 + lambda ||x^0||_1
+            const float2 *xi0 = a.X + (size_t)pix * l;
+            float l1 = 0.0f;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) X[c] = Xp[c] = Gp[c] = make_float2(0.0f, 0.0f);
-        float bb = 0.0f;
-        for (int i = lane; i < n; i += 64) {
-            const float2 v = b[i];
-            R[i] = Rp[i] = make_float2(-v.x, -v.y);
-            bb += v.x * v.x + v.y * v.y;
+            for (int c = 0; c < NC; ++c) {
+                const int m = lane + 64 * c;
+                X[c] = Xp[c] = m < l ? xi0[m] : make_float2(0.0f, 0.0f);
+                Gp[c] = make_float2(0.0f, 0.0f);
+                D[m] = X[c];
+                l1 += sqrtf(X[c].x * X[c].x + X[c].y * X[c].y);
+            }
+            WAVE_SYNC();
+            forward();
+            ++n_fwd;
+            WAVE_SYNC();
+            float rr = 0.0f;
+            for (int i = lane; i < n; i += 64) {
+                const float2 v = b[i], w = W[i];
+                R[i] = Rp[i] = make_float2(w.x - v.x, w.y - v.y);
+                rr += (w.x - v.x) * (w.x - v.x) + (w.y - v.y) * (w.y - v.y);
+            }
+            Fk = wsumf(rr) + lam * wsumf(l1);
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) X[c] = Xp[c] = Gp[c] = make_float2(0.0f, 0.0f);
+            float bb = 0.0f;
+            for (int i = lane; i < n; i += 64) {
+                const float2 v = b[i];
+                R[i] = Rp[i] = make_float2(-v.x, -v.y);
+                bb += v.x * v.x + v.y * v.y;
+            }
+            Fk = wsumf(bb);
         }
-        float Fk = wsumf(bb);
         WAVE_SYNC();
         adjoint();
         ++n_adj;
@@ -150,34 +204,11 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
                 d2 = wsumf(d2);
                 dl1 = wsumf(dl1);
                 WAVE_SYNC();
-                // w = A d: lanes over rows (rpl lanes per row when N is small, each
-                // taking every rpl-th column), A read through its transposed copy so
-                // that the lanes' loads are contiguous
-                float w2 = 0.0f;
-                for (int i0 = 0; i0 < n; i0 += rows_per_pass) {
-                    const int i = i0 + lane % rows_per_pass, part = lane / rows_per_pass;
-                    float wr = 0.0f, wi = 0.0f;
-                    if (i < n) {
-                        for (int j = part; j < l; j += rpl) {
-                            const float2 av = a.At[(size_t)j * n + i], dv = D[j];
-                            wr = fmaf(av.x, dv.x, fmaf(-av.y, dv.y, wr));
-                            wi = fmaf(av.x, dv.y, fmaf(av.y, dv.x, wi));
-                        }
-                    }
-                    for (int o = rows_per_pass; o < 64; o <<= 1) {
-                        wr += __shfl_xor(wr, o, 64);
-                        wi += __shfl_xor(wi, o, 64);
-                    }
-                    if (i < n && part == 0) {
-                        W[i] = make_float2(wr, wi);
-                        w2 += wr * wr + wi * wi;
-                    }
-                }
-                w2 = wsumf(w2);
+                const float w2 = forward();
                 ++n_fwd;
                 WAVE_SYNC();
                 if (!(a.backtracking && w2 > d2 / (2.0f * alpha) && alpha > afloor)) break;
-                if (k == 1 && trial == 0) {
+                if (k == 1 && trial == 0 && !a.warm) {
                     // First iteration: y = 0, so x-bar(alpha) = alpha S_lambda(-G_0) is linear in
                     // alpha and Eq. (15) reads alpha <= ||d||^2 / (2 ||A d||^2) at every alpha:
                     // jump to where the shrink sequence ends and scale d, A d, ||x-bar||_1.

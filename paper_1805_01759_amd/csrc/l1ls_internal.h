@@ -48,6 +48,7 @@ struct FistaArgs {
     int32_t fista_cap;        // retire unsolved pixels after this many iterations
     float tol, c_alpha;
     int32_t backtracking, monotone, polish;
+    int32_t warm;             // 1: X holds each pixel's initial point x^(0) on entry
 };
 
 // Per-block constants of the block-coordinate form (J <= kMaxBlocks).
@@ -135,6 +136,7 @@ hipError_t launch_setup_bin_gram(int n, int l, const float2 *A, double2 *H, hipS
 hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s,
                         bool *keeps_residual = nullptr);
 hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s);
+bool fista_split_kernel(const FistaArgs &a, int precision);
 hipError_t launch_setup_blocks(int n, int l, int J, const float2 *A, BlockConsts *bc, hipStream_t s);
 hipError_t launch_fista_blocks(const BlocksArgs &ba, hipStream_t s);
 size_t fista_blocks_lds(int n, int l_pad, int J);

@@ -71,7 +71,7 @@ def test_argument_errors_before_any_launch(L):
     assert _solve(L, wsb=16) == -3             # workspace too small
     assert _solve(L, stride=-1) == -1
     for field, val in [("tol", 0.0), ("tol", float("nan")), ("c_alpha", 1.0), ("c_alpha", 0.0),
-                       ("max_iter", -1), ("precision", 7), ("warm_start", 1), ("fp64_polish", 3)]:
+                       ("max_iter", -1), ("precision", 7), ("warm_start", 2), ("fp64_polish", 3)]:
         o = L.l1ls_options_default()
         setattr(o, field, val)
         assert _solve(L, o=o) == -1, field
@@ -94,3 +94,18 @@ def test_noalloc_size_limit_checked_on_host(L):
     assert L.l1ls_solve_noalloc(25, 256, 10, None, None, None, 0, None, None, None, None) == -1
     assert L.l1ls_solve_noalloc(200, 256, 10, None, None, None, 0, ctypes.byref(o), None, None,
                                 None) == -2
+
+
+def test_warm_start_refused_where_unsupported(L):
+    # Algorithm 1 from X runs in the split re/im MFMA kernels and the wave kernel:
+    # split-BF16 with l > 256 and the block form refuse it before any launch
+    o = L.l1ls_options_default()
+    o.warm_start = 1
+    o.precision = 1
+    assert _solve(L, n=4, l=512, o=o, wsb=1 << 26) == -2
+    assert b"warm_start" in L.l1ls_last_error()
+    o.precision = 0
+    st = L.l1ls_solve_blocks(4, 8, 3, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(64), 0,
+                             ctypes.byref(o), 2, ctypes.c_void_p(512), ctypes.c_void_p(128), None,
+                             ctypes.c_void_p(256), 1 << 20, None)
+    assert st == -2 and b"block form" in L.l1ls_last_error()
