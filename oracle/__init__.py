@@ -79,6 +79,8 @@ def lib():
         L.orc_rbpg.restype = None
         L.orc_polish.argtypes = [I, I, P, P, D, D, P]
         L.orc_polish.restype = I
+        L.orc_gap_screen.argtypes = [I, I, P, P, D, P, P, P]
+        L.orc_gap_screen.restype = I
         L.orc_rbpg_batch.argtypes = [I, I, I64, P, P, P, I64, ctypes.POINTER(RbpgOpts), I,
                                      P, P, P, P]
         L.orc_rbpg_batch.restype = None
@@ -148,6 +150,17 @@ def kkt_sub(A, b, lam, x) -> float:
 def dual_gap(A, b, lam, x) -> float:
     A, b, x = _c128(A), _c128(b), _c128(x)
     return float(lib().orc_dual_gap(A.shape[0], A.shape[1], _ptr(A), _ptr(b), float(lam), _ptr(x)))
+
+
+def gap_screen(A, b, lam, x):
+    """Gap-safe screening at x: (mask of bins whose minimiser entry is certainly 0,
+    duality gap F(x) - D(nu))."""
+    A, b, x = _c128(A), _c128(b), _c128(x)
+    n, l = A.shape
+    mask = np.zeros(l, np.int32)
+    gap = ctypes.c_double(0.0)
+    lib().orc_gap_screen(n, l, _ptr(A), _ptr(b), float(lam), _ptr(x), _ptr(mask), ctypes.byref(gap))
+    return mask.astype(bool), gap.value
 
 
 def rbpg(A, b, lam, *, tol=1e-4, max_iter=500, c_alpha=0.5, alpha0=0.0,

@@ -201,6 +201,33 @@ double orc_dual_gap(int n, int l, const ocplx *A, const ocplx *b, double lambda,
     return F - D;
 }
 
+int orc_gap_screen(int n, int l, const ocplx *A, const ocplx *b, double lambda, const ocplx *x,
+                   int *mask, double *gap_out)
+{
+    ocplx *r = malloc(sizeof(ocplx) * n), *g = malloc(sizeof(ocplx) * l);
+    residual(n, l, A, b, x, r);
+    grad_from_residual(n, l, A, r, g); /* g_l = 2 a_l^H r = a_l^H (2 r) */
+    double gmax = 0;
+    for (int j = 0; j < l; ++j) gmax = fmax(gmax, cabs(g[j]));
+    const double s = (gmax > lambda) ? lambda / gmax : 1.0;
+    const double gap = orc_dual_gap(n, l, A, b, lambda, x);
+    const double rad = 2.0 * sqrt(fmax(gap, 0.0));
+    int count = 0;
+    for (int j = 0; j < l; ++j) {
+        double an = 0;
+        for (int i = 0; i < n; ++i) an += cabs2(A[(int64_t)i * l + j]);
+        /* a relative margin of 1e-9 covers the rounding of s |g_l| and of the gap:
+         * at a minimiser the support bins sit exactly on |a_l^H nu*| = lambda */
+        const int out = s * cabs(g[j]) + sqrt(an) * rad < lambda * (1.0 - 1e-9);
+        mask[j] = out;
+        count += out;
+    }
+    if (gap_out) *gap_out = gap;
+    free(r);
+    free(g);
+    return count;
+}
+
 /* ---------------------------------------------- Algorithm 1, one block J=1 */
 
 void orc_rbpg(int n, int l, const ocplx *A, const ocplx *b, double lambda, double Lf,

@@ -61,6 +61,16 @@ double orc_kkt_sub(int n, int l, const ocplx *A, const ocplx *b, double lambda,
 double orc_dual_gap(int n, int l, const ocplx *A, const ocplx *b, double lambda,
                     const ocplx *x);
 
+/* Gap-safe column screening from the dual point of x (not in the paper): with
+ * nu = s 2 (Ax - b) as in orc_dual_gap, D is 1/2-strongly concave, so
+ * ||nu - nu*|| <= 2 sqrt(F(x) - D(nu)), and |a_l^H nu*| <= |a_l^H nu| + 2 ||a_l|| sqrt(gap).
+ * Where that bound is below lambda (1 - 1e-9), the optimality conditions of
+ * Eq. (1) force x*_l = 0: mask[l] = 1 (else 0); the relative margin covers the
+ * rounding of the bound.  Returns the number of screened bins; gap_out
+ * (may be NULL) receives F(x) - D(nu). */
+int orc_gap_screen(int n, int l, const ocplx *A, const ocplx *b, double lambda, const ocplx *x,
+                   int *mask, double *gap_out);
+
 /* Options of Algorithm 1 with J = 1 (full gradient). */
 typedef struct {
     double alpha0;   /* initial step; <= 0 selects 1/(2 max_l ||a_l||^2)          */
