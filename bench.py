@@ -67,6 +67,14 @@ PARITY_SAMPLE = {"scene": 1024, "pairs": 512, "tiny": 1024, "motion": 512, "moti
                  "superres": 960}
 PARITY_BAR = {"fp32": 1e-4, "split_bf16": 1e-3}
 POLISH_AFTER = 12          # FP32 iterations before a pixel goes to the FP64 stage
+# per workload where another budget is faster (measured with every pixel refined:
+# close pairs 2.46 / 2.60 / 2.61 / 2.62 M solved pixels/s at 12 / 8 / 6 / 4; the
+# scene is fastest at 12)
+POLISH_AFTER_BY_WORKLOAD = {"pairs": 6}
+
+
+def polish_after_for(workload: str) -> int:
+    return POLISH_AFTER_BY_WORKLOAD.get(workload, POLISH_AFTER)
 # FP64 refinement of every pixel to FP64 accuracy (fp64_polish = 2): the mode in
 # which the returned x matches the certified minimiser to the stated bar
 ACCURACY_MODE = 2
@@ -433,7 +441,8 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=5,
                     help="timed steps of the other precision (at most --steps)")
     ap.add_argument("--max-iter", type=int, default=500)
-    ap.add_argument("--polish-after", type=int, default=POLISH_AFTER)
+    ap.add_argument("--polish-after", type=int, default=0,
+                    help="FP32 iterations before the FP64 stage (0: the workload's default)")
     ap.add_argument("--polish", type=int, default=ACCURACY_MODE,
                     help="fp64_polish: 1 refine pixels above tol, 2 every pixel to FP64 accuracy")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -445,6 +454,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.polish_after <= 0:
+        args.polish_after = polish_after_for(args.workload)
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (pixels are "
               "independent; see the sharding note in DESIGN.md). Run with --gpus 1.",

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -24,59 +25,6 @@ static l1ls_status fail(l1ls_status st, const char *fmt, ...)
     return st;
 }
 
-static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-int slice_blocks_for(int l) { return l <= 256 ? 8 : 16; }
-int waves_for(int l)
-{
-    const int slice = 8 * slice_blocks_for(l);
-    return (l + slice - 1) / slice;
-}
-int lpad_for(int l) { return waves_for(l) * 8 * slice_blocks_for(l); }
-int zblocks_for(int n) { return (2 * n + 15) / 16; }
-int rows_pad_for(int n) { return 16 * ((n + 15) / 16); }
-
-StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
-{
-    StackWorkspace w;
-    const int l_pad = lpad_for(l);
-    size_t off = 0;
-    w.a_packed = off;
-    off = align_up(off + (size_t)rows_pad_for(n) * l_pad * sizeof(float2), 256);
-    w.a_trans = off;
-    off = align_up(off + (size_t)l_pad * n * sizeof(float2), 256);
-    w.gram = off;
-    off = align_up(off + (size_t)n * n * sizeof(double2), 256);
-    w.consts = off;
-    off = align_up(off + sizeof(StackConsts), 256);
-    w.queue = off;
-    off = align_up(off + 8 * sizeof(uint32_t), 256);
-    w.work = off;
-    off = align_up(off + 4 * sizeof(unsigned long long), 256);
-    w.status = off;
-    off = align_up(off + (size_t)p * sizeof(uint32_t), 256);
-    w.iters = off;
-    off = align_up(off + (size_t)p * sizeof(int32_t), 256);
-    w.kkt32 = off;
-    off = align_up(off + (size_t)p * sizeof(float), 256);
-    w.polish_list = off;
-    off = align_up(off + (size_t)p * sizeof(int32_t), 256);
-    w.blocks = off;
-    off = align_up(off + (size_t)kMaxBlocks * sizeof(BlockConsts), 256);
-    w.resid = off;
-    off = align_up(off + (size_t)p * n * sizeof(float2), 256);
-    w.overflow = off;
-    off = align_up(off + (size_t)p * sizeof(int32_t), 256);
-    // the refinement's bin Gram A^H A and the A^H b of its workgroups' pixels
-    w.hgram = off;
-    off = align_up(off + (size_t)l * l * sizeof(double2), 256);
-    w.cbuf = off;
-    const int64_t groups = p < kMaxRefineGroups ? p : kMaxRefineGroups;
-    off = align_up(off + (size_t)groups * l * sizeof(double2), 256);
-    w.total = off;
-    return w;
-}
-
 // Largest supported shapes: the register-resident MFMA kernel takes N <= 64,
 // L <= 512; the wave-per-pixel kernel takes the rest up to N = 128, L = 1024.
 constexpr int kMaxNSolve = 128;
@@ -93,7 +41,7 @@ l1ls_status set_error(l1ls_status st, const char *fmt, ...)
     return st;
 }
 
-static l1ls_status check_options(const l1ls_options *o)
+l1ls_status check_options(const l1ls_options *o)
 {
     if (!o) return fail(L1LS_ERR_INVALID_ARG, "options pointer is NULL");
     if (o->max_iter < 0) return fail(L1LS_ERR_INVALID_ARG, "max_iter must be >= 0 (got %d)", o->max_iter);
@@ -152,14 +100,26 @@ struct TimedLaunch {
     }
 };
 
-l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
-                        const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
-                        l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
-                        hipStream_t s, int choice, int blocks, const double *draws)
+SolveOpts solve_opts(const l1ls_options *opt)
+{
+    SolveOpts o{};
+    int cap = opt->max_iter;
+    if (opt->polish_after > 0 && opt->polish_after < cap) cap = opt->polish_after;
+    o.fista_cap = cap;
+    o.tol = opt->tol;
+    o.c_alpha = opt->c_alpha;
+    o.backtracking = opt->backtracking ? 1 : 0;
+    o.monotone = opt->monotone ? 1 : 0;
+    o.polish = opt->fp64_polish;
+    o.warm = opt->warm_start;
+    return o;
+}
+
+// Checks of one stack's arguments before anything is queued.
+l1ls_status check_stack(int32_t n, int32_t l, int64_t p, const void *A, const void *B, const float *lambda,
+                        int64_t lambda_stride, const void *X, const void *ws, size_t ws_bytes)
 {
     l1ls_status st = check_shape(n, l, p);
-    if (st != L1LS_OK) return st;
-    st = check_options(opt);
     if (st != L1LS_OK) return st;
     if (p == 0) return L1LS_OK;
     if (!A || !B || !lambda || !X || !ws) return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
@@ -167,162 +127,158 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         return fail(L1LS_ERR_INVALID_ARG, "A, B, X must be 8-byte aligned and lambda 4-byte aligned");
     if (!aligned(ws, 256)) return fail(L1LS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (lambda_stride < 0) return fail(L1LS_ERR_INVALID_ARG, "lambda_stride must be >= 0");
-    const StackWorkspace lay = stack_workspace_layout(n, l, p);
-    if (ws_bytes < lay.total)
-        return fail(L1LS_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
+    const size_t need = stack_workspace_layout(n, l, p).total;
+    if (ws_bytes < need) return fail(L1LS_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return L1LS_OK;
+}
 
-    char *w = (char *)ws;
-    const int waves = waves_for(l), l_pad = lpad_for(l);
-    if (opt->warm_start) {
-        // Algorithm 1 from X runs in the split re/im MFMA kernels and the wave kernel
-        if (choice == kBlocks)
-            return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "warm_start is not available in the block form");
-        FistaArgs probe{};
-        probe.n = n;
-        probe.l = l;
-        probe.l_pad = l_pad;
-        probe.waves = waves;
-        const int ch = choice == kAuto ? (mfma_supports(n, l) ? kMfma : kWave) : choice;
-        if (ch == kMfma && !fista_split_kernel(probe, opt->precision))
-            return fail(L1LS_ERR_UNSUPPORTED_SHAPE,
-                        "warm_start with split-BF16 needs l <= 256 (n = %d, l = %d)", n, l);
+// The iteration variant of a stack (choice kAuto / kMfma / kWave, `alt` an
+// alternative tiling); warm starts need the split re/im or the wave kernel.
+l1ls_status stack_variant(int32_t n, int32_t l, const l1ls_options *opt, int choice, int alt, IterVariant *v)
+{
+    if (choice == kMfma && !mfma_supports(n, l))
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
+    if (!iter_variant(n, l, opt->precision, choice, alt, v))
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "no iteration kernel variant %d for n = %d, l = %d", alt, n, l);
+    if (opt->warm_start && v->family == kVarEmbedded)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "warm_start with split-BF16 needs l <= 256 (n = %d, l = %d)",
+                    n, l);
+    return L1LS_OK;
+}
+
+StackDesc stack_desc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B, const float *lambda,
+                     int64_t lambda_stride, l1ls_c32 *X, const l1ls_diag *diag, void *ws, const IterVariant &v)
+{
+    StackDesc d{};
+    d.A = (const float2 *)A;
+    d.B = (const float2 *)B;
+    d.lambda = lambda;
+    d.X = (float2 *)X;
+    d.ws = (char *)ws;
+    if (diag) {
+        d.iters = diag->iters;
+        d.kkt = diag->kkt;
+        d.objective = diag->objective;
+        d.status = diag->status;
+        d.nnz = diag->nnz;
     }
-    float2 *Ap = (float2 *)(w + lay.a_packed);
-    double2 *gram = (double2 *)(w + lay.gram);
-    StackConsts *consts = (StackConsts *)(w + lay.consts);
-    uint32_t *queue = (uint32_t *)(w + lay.queue);
-    uint32_t *status_ws = (uint32_t *)(w + lay.status);
-    int32_t *iters_ws = (int32_t *)(w + lay.iters);
-    float *kkt32 = (float *)(w + lay.kkt32);
-    int32_t *plist = (int32_t *)(w + lay.polish_list);
+    d.p = p;
+    d.lambda_stride = lambda_stride;
+    d.n = n;
+    d.l = l;
+    d.keep_residual = v.family == kVarMfma ? 1 : 0;
+    return d;
+}
 
-    unsigned long long *work = (unsigned long long *)(w + lay.work);
-    float2 *At = (float2 *)(w + lay.a_trans);
-    hipError_t e = launch_setup(n, l, l_pad, (const float2 *)A, Ap, At, gram, consts, queue, work, s);
+// Queue the whole solve of `count` stacks (their variants in `var`): setup of
+// every stack, one iteration launch per variant (tables of up to
+// kMaxStacksPerLaunch), the two refinement passes and the certificate.
+l1ls_status run_stacks(const StackDesc *d, const IterVariant *var, int count, const l1ls_options *opt,
+                       hipStream_t s)
+{
+    const SolveOpts o = solve_opts(opt);
+    auto chunks = [&](auto &&fn) -> hipError_t {
+        StackTable t{};
+        t.o = o;
+        for (int i = 0; i < count; i += kMaxStacksPerLaunch) {
+            t.count = std::min(kMaxStacksPerLaunch, count - i);
+            for (int k = 0; k < t.count; ++k) t.d[k] = d[i + k];
+            const hipError_t e = fn(t);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = chunks([&](const StackTable &t) { return launch_setup_table(t, opt->fp64_polish != 0, s); });
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "setup launch: %s", hipGetErrorString(e));
-
-    FistaArgs fa;
-    fa.n = n;
-    fa.l = l;
-    fa.l_pad = l_pad;
-    fa.waves = waves;
-    fa.p = p;
-    fa.A = Ap;
-    fa.At = At;
-    fa.B = (const float2 *)B;
-    fa.lambda = lambda;
-    fa.lambda_stride = lambda_stride;
-    fa.X = (float2 *)X;
-    fa.iters = iters_ws;
-    fa.kkt32 = kkt32;
-    fa.status = status_ws;
-    fa.consts = consts;
-    fa.queue = queue;
-    fa.polish_count = queue + 1;
-    fa.polish_list = plist;
-    fa.work = work;
-    fa.R = nullptr;
-    int cap = opt->max_iter;
-    if (opt->polish_after > 0 && opt->polish_after < cap) cap = opt->polish_after;
-    fa.fista_cap = cap;
-    fa.tol = opt->tol;
-    fa.c_alpha = opt->c_alpha;
-    fa.backtracking = opt->backtracking ? 1 : 0;
-    fa.monotone = opt->monotone ? 1 : 0;
-    fa.polish = opt->fp64_polish;
-    fa.warm = opt->warm_start;
-    if (choice == kBlocks) {
-        BlocksArgs ba;
-        ba.f = fa;
-        ba.J = blocks;
-        ba.u = draws;
-        ba.bc = (const BlockConsts *)(w + lay.blocks);
-        e = launch_setup_blocks(n, l, blocks, (const float2 *)A, (BlockConsts *)(w + lay.blocks), s);
-        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "block setup launch: %s", hipGetErrorString(e));
-        TimedLaunch t(s, L1LS_KERNEL_ITERATION);
-        e = launch_fista_blocks(ba, s);
-    } else {
-        if (choice == kAuto) choice = mfma_supports(n, l) ? kMfma : kWave;
-        if (choice == kMfma && !mfma_supports(n, l))
-            return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
-        // the split re/im MFMA kernels keep the residual of each retired pixel
-        bool keeps = false;
-        if (choice == kMfma) fa.R = (float2 *)(w + lay.resid);
-        TimedLaunch t(s, L1LS_KERNEL_ITERATION);
-        e = choice == kMfma ? launch_fista(fa, opt->precision, 0, s, &keeps) : launch_fista_wave(fa, s);
-        if (!keeps) fa.R = nullptr;
+    {
+        TimedLaunch tl(s, L1LS_KERNEL_ITERATION);
+        std::vector<bool> done(count, false);
+        for (int i = 0; i < count && e == hipSuccess; ++i) {
+            if (done[i]) continue;
+            StackTable t{};
+            t.o = o;
+            for (int k = i; k < count && e == hipSuccess; ++k) {
+                if (done[k] || !(var[k] == var[i])) continue;
+                done[k] = true;
+                t.d[t.count++] = d[k];
+                if (t.count == kMaxStacksPerLaunch) {
+                    e = launch_iteration_table(t, var[i], s);
+                    t.count = 0;
+                }
+            }
+            if (e == hipSuccess && t.count > 0) e = launch_iteration_table(t, var[i], s);
+        }
     }
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
-
     if (opt->fp64_polish) {
-        e = launch_setup_bin_gram(n, l, (const float2 *)A, (double2 *)(w + lay.hgram), s);
-        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "bin Gram launch: %s", hipGetErrorString(e));
-        PolishArgsDev pa;
-        pa.n = n;
-        pa.l = l;
-        pa.l_pad = l_pad;
-        pa.A = Ap;
-        pa.B = (const float2 *)B;
-        pa.lambda = lambda;
-        pa.lambda_stride = lambda_stride;
-        pa.X = (float2 *)X;
-        pa.consts = consts;
-        pa.count = queue + 1;
-        pa.next = queue + 2;
-        pa.list = plist;
-        pa.R = fa.R;
-        pa.overflow = (int32_t *)(w + lay.overflow);
-        pa.overflow_count = queue + 3;
-        pa.status = status_ws;
-        pa.rounds = 64;
-        pa.mode = opt->fp64_polish;
-        pa.tol = opt->tol;
-        pa.work = work;
-        pa.H = (const double2 *)(w + lay.hgram);
-        pa.cbuf = (double2 *)(w + lay.cbuf);
-        pa.max_groups = (int)(p < kMaxRefineGroups ? p : kMaxRefineGroups);
-        int dev = 0, cus = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        TimedLaunch t(s, L1LS_KERNEL_REFINE);
-        e = launch_polish(pa, cus * 8, s);
-        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "polish launch: %s", hipGetErrorString(e));
+        TimedLaunch tl(s, L1LS_KERNEL_REFINE);
+        e = chunks([&](const StackTable &t) { return launch_polish_table(t, s); });
         // pixels whose 16-slot working set filled above tol: the 32-slot pass starts
         // from the point the first one left in X (its FP64 objective is recomputed)
-        PolishArgsDev pw = pa;
-        pw.count = queue + 3;
-        pw.next = queue + 4;
-        pw.list = pa.overflow;
-        pw.R = nullptr;
-        pw.overflow = nullptr;
-        pw.overflow_count = nullptr;
-        e = launch_polish_wide(pw, cus * 4, s);
-        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "wide polish launch: %s", hipGetErrorString(e));
+        if (e == hipSuccess) e = chunks([&](const StackTable &t) { return launch_polish_wide_table(t, s); });
+        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "refinement launch: %s", hipGetErrorString(e));
     }
-
-    CertifyArgs ca;
-    ca.n = n;
-    ca.l = l;
-    ca.l_pad = l_pad;
-    ca.p = p;
-    ca.A = Ap;
-    ca.B = (const float2 *)B;
-    ca.lambda = lambda;
-    ca.lambda_stride = lambda_stride;
-    ca.X = (float2 *)X;
-    ca.iters_in = iters_ws;
-    ca.status_in = status_ws;
-    ca.consts = consts;
-    ca.tol = opt->tol;
-    ca.polish = opt->fp64_polish;
-    ca.iters = diag ? diag->iters : nullptr;
-    ca.kkt = diag ? diag->kkt : nullptr;
-    ca.objective = diag ? diag->objective : nullptr;
-    ca.status = diag ? diag->status : nullptr;
-    ca.nnz = diag ? diag->nnz : nullptr;
     {
-        TimedLaunch t(s, L1LS_KERNEL_CERTIFY);
-        e = launch_certify(ca, s);
+        TimedLaunch tl(s, L1LS_KERNEL_CERTIFY);
+        e = chunks([&](const StackTable &t) { return launch_certify_table(t, s); });
+    }
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "certify launch: %s", hipGetErrorString(e));
+    return L1LS_OK;
+}
+
+l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
+                        const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
+                        l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
+                        hipStream_t s, int choice, int blocks, const double *draws, int alt)
+{
+    l1ls_status st = check_shape(n, l, p);
+    if (st != L1LS_OK) return st;
+    st = check_options(opt);
+    if (st != L1LS_OK) return st;
+    if (p == 0) return L1LS_OK;
+    st = check_stack(n, l, p, A, B, lambda, lambda_stride, X, ws, ws_bytes);
+    if (st != L1LS_OK) return st;
+    if (choice != kBlocks) {
+        IterVariant v;
+        st = stack_variant(n, l, opt, choice, alt, &v);
+        if (st != L1LS_OK) return st;
+        const StackDesc d = stack_desc(n, l, p, A, B, lambda, lambda_stride, X, diag, ws, v);
+        return run_stacks(&d, &v, 1, opt, s);
+    }
+    // Algorithm 1 with J column blocks: its own iteration kernel, then the same
+    // refinement and certificate
+    if (opt->warm_start) return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "warm_start is not available in the block form");
+    IterVariant none{};
+    const StackDesc d = stack_desc(n, l, p, A, B, lambda, lambda_stride, X, diag, ws, none);
+    const SolveOpts o = solve_opts(opt);
+    StackTable t{};
+    t.count = 1;
+    t.o = o;
+    t.d[0] = d;
+    hipError_t e = launch_setup_table(t, opt->fp64_polish != 0, s);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "setup launch: %s", hipGetErrorString(e));
+    const StackWorkspace lay = stack_workspace_layout(n, l, p);
+    BlocksArgs ba;
+    ba.f = fista_args_for(d, o);
+    ba.J = blocks;
+    ba.u = draws;
+    ba.bc = (const BlockConsts *)((char *)ws + lay.blocks);
+    e = launch_setup_blocks(n, l, blocks, (const float2 *)A, (BlockConsts *)((char *)ws + lay.blocks), s);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "block setup launch: %s", hipGetErrorString(e));
+    {
+        TimedLaunch tl(s, L1LS_KERNEL_ITERATION);
+        e = launch_fista_blocks(ba, s);
+    }
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "iteration launch: %s", hipGetErrorString(e));
+    if (opt->fp64_polish) {
+        TimedLaunch tl(s, L1LS_KERNEL_REFINE);
+        e = launch_polish_table(t, s);
+        if (e == hipSuccess) e = launch_polish_wide_table(t, s);
+        if (e != hipSuccess) return fail(L1LS_ERR_HIP, "refinement launch: %s", hipGetErrorString(e));
+    }
+    {
+        TimedLaunch tl(s, L1LS_KERNEL_CERTIFY);
+        e = launch_certify_table(t, s);
     }
     if (e != hipSuccess) return fail(L1LS_ERR_HIP, "certify launch: %s", hipGetErrorString(e));
     return L1LS_OK;

@@ -11,14 +11,10 @@
 
 namespace l1ls {
 
-__global__ void __launch_bounds__(64) certify_kernel(const CertifyArgs a)
+__device__ __forceinline__ void certify_pixel(const CertifyArgs &a, int64_t p, float2 *sx, double2 *sr,
+                                              int16_t *snz)
 {
-    __shared__ float2 sx[64 * kMaxWaves];
-    __shared__ double2 sr[kMaxN];
-    __shared__ int16_t snz[64 * kMaxWaves];
     const int lane = threadIdx.x;
-    const int64_t p = blockIdx.x;
-    if (p >= a.p) return;
     const int n = a.n, l = a.l, ld = a.l_pad;
     const double lf = a.consts->lf, inv_lf = 1.0 / lf;
     const float lam_f = a.lambda[p * a.lambda_stride];
@@ -131,10 +127,30 @@ __global__ void __launch_bounds__(64) certify_kernel(const CertifyArgs a)
     }
 }
 
-hipError_t launch_certify(const CertifyArgs &a, hipStream_t s)
+// One workgroup a pixel for up to 2^25 pixels a stack, grid-stride beyond (the
+// grid stays within the dispatch limits at any pixel count); stacks in table order.
+__global__ void __launch_bounds__(64) certify_kernel(const StackTable t)
 {
-    if (a.p <= 0) return hipSuccess;
-    hipLaunchKernelGGL(certify_kernel, dim3((unsigned)a.p), dim3(64), 0, s, a);
+    __shared__ float2 sx[64 * kMaxWaves];
+    __shared__ double2 sr[kMaxN];
+    __shared__ int16_t snz[64 * kMaxWaves];
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        const CertifyArgs a = certify_args_for(t.d[i], t.o);
+        for (int64_t p = blockIdx.x; p < a.p; p += gridDim.x) {
+            certify_pixel(a, p, sx, sr, snz);
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_certify_table(const StackTable &t, hipStream_t s)
+{
+    int64_t g = 0;
+    for (int i = 0; i < t.count; ++i) g = t.d[i].p > g ? t.d[i].p : g;
+    if (g == 0) return hipSuccess;
+    if (g > ((int64_t)1 << 25)) g = (int64_t)1 << 25;
+    hipLaunchKernelGGL(certify_kernel, dim3((unsigned)g), dim3(64), 0, s, t);
     return hipGetLastError();
 }
 

@@ -1,5 +1,7 @@
 // Setup kernel (packing, Lipschitz constant, alpha0) and the dispatch from
 // (N, L, precision) to the instantiated persistent iteration kernels.
+#include <algorithm>
+
 #include "l1ls_internal.h"
 
 namespace l1ls {
@@ -7,8 +9,10 @@ namespace l1ls {
 template <int NZB, int KB, bool ALDS, int PREC>
 hipError_t launch_one(const FistaArgs &a, int max_groups, hipStream_t s);
 template <int T, int KB, bool ALDS, int PREC, int WMAX>
-hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s);
+hipError_t launch_mfma_one(const StackTable &t, int waves, hipStream_t s);
 size_t fm_bf_planes_bytes_host(int rows, int l_pad);
+hipError_t launch_wave_table(const StackTable &t, int nc, hipStream_t s);
+int wave_chunks(int l);
 
 __device__ __forceinline__ int rows_pad_for_dev(int n) { return 16 * ((n + 15) / 16); }
 
@@ -19,9 +23,41 @@ __device__ __forceinline__ int rows_pad_for_dev(int n) { return 16 * ((n + 15) /
 //   setup_gram_kernel   (grid)    FP64 Gram M = A A^H, one entry per thread
 //   setup_power_kernel  (1 group) queue/counter reset, alpha0 = 1/(2 max_l ||a_l||^2),
 //                                 L_f = 2 lambda_max(M) by FP64 power iteration
-__global__ void __launch_bounds__(256) setup_pack_kernel(int n, int l, int l_pad, const float2 *A,
-                                                         float2 *Ap, float2 *At)
+// Pointers of stack blockIdx.y's setup inputs and outputs.
+struct SetupView {
+    int n, l, l_pad;
+    const float2 *A;
+    float2 *Ap, *At;
+    double2 *gram, *H;
+    StackConsts *consts;
+    uint32_t *queue;
+    unsigned long long *work;
+};
+__device__ inline SetupView setup_view(const StackDesc &d)
 {
+    const StackWorkspace lay = stack_workspace_layout(d.n, d.l, d.p);
+    SetupView v;
+    v.n = d.n;
+    v.l = d.l;
+    v.l_pad = lpad_for(d.l);
+    v.A = d.A;
+    v.Ap = (float2 *)(d.ws + lay.a_packed);
+    v.At = (float2 *)(d.ws + lay.a_trans);
+    v.gram = (double2 *)(d.ws + lay.gram);
+    v.H = (double2 *)(d.ws + lay.hgram);
+    v.consts = (StackConsts *)(d.ws + lay.consts);
+    v.queue = (uint32_t *)(d.ws + lay.queue);
+    v.work = (unsigned long long *)(d.ws + lay.work);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) setup_pack_kernel(const StackTable t)
+{
+    if (t.d[blockIdx.y].p <= 0) return;
+    const SetupView sv = setup_view(t.d[blockIdx.y]);
+    const int n = sv.n, l = sv.l, l_pad = sv.l_pad;
+    const float2 *A = sv.A;
+    float2 *Ap = sv.Ap, *At = sv.At;
     const int rows = rows_pad_for_dev(n);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)rows * l_pad; idx += stride) {
@@ -34,24 +70,35 @@ __global__ void __launch_bounds__(256) setup_pack_kernel(int n, int l, int l_pad
     }
 }
 
-__global__ void __launch_bounds__(256) setup_gram_kernel(int n, int l, const float2 *A, double2 *M)
+__global__ void __launch_bounds__(256) setup_gram_kernel(const StackTable t)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * n) return;
-    const int i = e / n, kk = e % n;
-    double sr = 0.0, si = 0.0;
-    for (int c = 0; c < l; ++c) {
-        const float2 p = A[(size_t)i * l + c], q = A[(size_t)kk * l + c];
-        sr += (double)p.x * q.x + (double)p.y * q.y;  // p conj(q)
-        si += (double)p.y * q.x - (double)p.x * q.y;
+    if (t.d[blockIdx.y].p <= 0) return;
+    const SetupView sv = setup_view(t.d[blockIdx.y]);
+    const int n = sv.n, l = sv.l;
+    const float2 *A = sv.A;
+    double2 *M = sv.gram;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+        const int i = e / n, kk = e % n;
+        double sr = 0.0, si = 0.0;
+        for (int c = 0; c < l; ++c) {
+            const float2 p = A[(size_t)i * l + c], q = A[(size_t)kk * l + c];
+            sr += (double)p.x * q.x + (double)p.y * q.y;  // p conj(q)
+            si += (double)p.y * q.x - (double)p.x * q.y;
+        }
+        M[e] = make_double2(sr, si);
     }
-    M[e] = make_double2(sr, si);
 }
 
-__global__ void __launch_bounds__(256) setup_power_kernel(int n, int l, const float2 *A, const double2 *M,
-                                                          StackConsts *consts, uint32_t *queue,
-                                                          unsigned long long *work)
+__global__ void __launch_bounds__(256) setup_power_kernel(const StackTable t)
 {
+    if (t.d[blockIdx.y].p <= 0) return;
+    const SetupView sv = setup_view(t.d[blockIdx.y]);
+    const int n = sv.n, l = sv.l;
+    const float2 *A = sv.A;
+    const double2 *M = sv.gram;
+    StackConsts *consts = sv.consts;
+    uint32_t *queue = sv.queue;
+    unsigned long long *work = sv.work;
     __shared__ double red[3][256];
     __shared__ double2 v[kMaxN];
     __shared__ double2 wv[kMaxN];
@@ -127,8 +174,13 @@ __global__ void __launch_bounds__(256) setup_power_kernel(int n, int l, const fl
 
 // Bin Gram H = A^H A (FP64, l x l, row s holds H[s][m] = a_s^H a_m) for the
 // refinement's round-end gradient; one entry per thread, m the fast index.
-__global__ void __launch_bounds__(256) setup_bin_gram_kernel(int n, int l, const float2 *A, double2 *H)
+__global__ void __launch_bounds__(256) setup_bin_gram_kernel(const StackTable t)
 {
+    if (t.d[blockIdx.y].p <= 0) return;
+    const SetupView sv = setup_view(t.d[blockIdx.y]);
+    const int n = sv.n, l = sv.l;
+    const float2 *A = sv.A;
+    double2 *H = sv.H;
     const int64_t total = (int64_t)l * l;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -143,12 +195,30 @@ __global__ void __launch_bounds__(256) setup_bin_gram_kernel(int n, int l, const
     }
 }
 
-hipError_t launch_setup_bin_gram(int n, int l, const float2 *A, double2 *H, hipStream_t s)
+// Setup of every stack of a table: packing, the N x N Gram, L_f and alpha_0 with
+// the queue and counter reset, and (for the refinement) the bin Gram.
+hipError_t launch_setup_table(const StackTable &t, bool bin_gram, hipStream_t s)
 {
-    const int64_t total = (int64_t)l * l;
-    int groups = (int)((total + 255) / 256);
-    if (groups > 4096) groups = 4096;
-    hipLaunchKernelGGL(setup_bin_gram_kernel, dim3(groups), dim3(256), 0, s, n, l, A, H);
+    if (t.count <= 0) return hipSuccess;
+    int64_t pack = 0, nn = 0, ll = 0;
+    for (int i = 0; i < t.count; ++i) {
+        const StackDesc &d = t.d[i];
+        pack = std::max<int64_t>(pack, (int64_t)rows_pad_for(d.n) * lpad_for(d.l));
+        nn = std::max<int64_t>(nn, (int64_t)d.n * d.n);
+        ll = std::max<int64_t>(ll, (int64_t)d.l * d.l);
+    }
+    const unsigned ys = (unsigned)t.count;
+    auto gx = [](int64_t e, int64_t cap) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((e + 255) / 256, cap)); };
+    hipLaunchKernelGGL(setup_pack_kernel, dim3(gx(pack, 1024), ys), dim3(256), 0, s, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(setup_gram_kernel, dim3(gx(nn, 64), ys), dim3(256), 0, s, t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(setup_power_kernel, dim3(1, ys), dim3(256), 0, s, t);
+    e = hipGetLastError();
+    if (e != hipSuccess || !bin_gram) return e;
+    hipLaunchKernelGGL(setup_bin_gram_kernel, dim3(gx(ll, 4096), ys), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 
@@ -167,23 +237,6 @@ bool fista_a_fits_lds(int n, int l_pad, int waves, int zb)
 {
     // one wave per SIMD: a workgroup of W waves may use W/4 of the CU's 160 KB
     return fista_lds_bytes(n, l_pad, waves, zb, true) <= (size_t)160 * 1024 * waves / 4;
-}
-
-hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, float2 *At, double2 *gram,
-                        StackConsts *consts, uint32_t *queue, unsigned long long *work,
-                        hipStream_t s)
-{
-    const int64_t elems = (int64_t)rows_pad_for(n) * l_pad;
-    int groups = (int)((elems + 255) / 256);
-    if (groups > 1024) groups = 1024;
-    hipLaunchKernelGGL(setup_pack_kernel, dim3(groups), dim3(256), 0, s, n, l, l_pad, A, Ap, At);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(setup_gram_kernel, dim3((n * n + 255) / 256), dim3(256), 0, s, n, l, A, gram);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(setup_power_kernel, dim3(1), dim3(256), 0, s, n, l, A, gram, consts, queue, work);
-    return hipGetLastError();
 }
 
 template <int NZB, int PREC>
@@ -236,65 +289,115 @@ static bool mfma_lds_fits(const FistaArgs &a, int precision)
     return fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, true, precision) <= cap;
 }
 
-template <int T>
-static hipError_t launch_mfma_t(const FistaArgs &a, int max_groups, hipStream_t s)
+bool mfma_supports(int n, int l);
+
+// The tiling a stack runs (see IterVariant).  FP32: up to 32 rows and 256 bins a
+// wave holds 32 unknowns and a workgroup up to eight waves (two per SIMD), else 64
+// (L <= 256) or 128 unknowns a wave and up to four waves; A is staged in LDS
+// where it fits.  Split-BF16 stages its bf16 planes of A in LDS (L <= 256) or
+// runs the real-embedded kernel.  Shapes beyond the MFMA kernels (N > 64 or
+// L > 512), or choice kWave, run the wave-per-pixel kernel.
+bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant *v)
 {
-    if constexpr (T <= 2) {
-        if (slice_blocks_for(a.l) == 8) {
-            // 32 unknowns per wave, up to eight waves: the state of a 16-pixel tile
-            // fits two waves per SIMD without accumulation-register traffic
-            FistaArgs b = a;
-            b.waves = a.l_pad / 32;
-            return mfma_lds_fits(b, L1LS_FP32) ? launch_mfma_one<T, 2, true, L1LS_FP32, 8>(b, max_groups, s)
-                                               : launch_mfma_one<T, 2, false, L1LS_FP32, 8>(b, max_groups, s);
-        }
+    IterVariant r{};
+    const int l_pad = lpad_for(l), waves = waves_for(l), T = rows_pad_for(n) / 16;
+    if (choice == kWave || !mfma_supports(n, l)) {
+        if (alt != 0) return false;
+        r.family = kVarWave;
+        r.nc = wave_chunks(l);
+        r.waves = 1;
+        r.prec = L1LS_FP32;
+        *v = r;
+        return r.nc > 0;
     }
-    const bool lds = mfma_lds_fits(a, L1LS_FP32);
-    if (slice_blocks_for(a.l) == 8)
-        return lds ? launch_mfma_one<T, 4, true, L1LS_FP32, 4>(a, max_groups, s)
-                   : launch_mfma_one<T, 4, false, L1LS_FP32, 4>(a, max_groups, s);
-    return lds ? launch_mfma_one<T, 8, true, L1LS_FP32, 4>(a, max_groups, s)
-               : launch_mfma_one<T, 8, false, L1LS_FP32, 4>(a, max_groups, s);
-}
-
-// Whether launch_fista runs a split re/im kernel (fista_mfma.h) for this shape
-// and precision; the real-embedded kernels (fista_impl.h) have no warm start.
-bool fista_split_kernel(const FistaArgs &a, int precision)
-{
-    const int T = rows_pad_for(a.n) / 16;
-    if (precision == L1LS_SPLIT_BF16) return slice_blocks_for(a.l) == 8 && mfma_lds_fits(a, L1LS_SPLIT_BF16) && T <= 4;
-    return T <= 4;
-}
-
-hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s, bool *keeps_residual)
-{
-    if (a.warm && !fista_split_kernel(a, precision)) return hipErrorNotSupported;
-    const int T = rows_pad_for(a.n) / 16;
-    // the split re/im kernels (fista_mfma.h) write a.R; the real-embedded ones do not
-    if (keeps_residual)
-        *keeps_residual = precision == L1LS_SPLIT_BF16
-                              ? (slice_blocks_for(a.l) == 8 && mfma_lds_fits(a, L1LS_SPLIT_BF16) && T <= 4)
-                              : T <= 4;
+    FistaArgs probe{};
+    probe.n = n;
+    probe.l = l;
+    probe.l_pad = l_pad;
+    probe.waves = waves;
     if (precision == L1LS_SPLIT_BF16) {
-        // split re/im layout with bf16 planes in LDS where they fit (64 unknowns per
-        // wave); otherwise the real-embedded kernel
-        if (slice_blocks_for(a.l) == 8 && mfma_lds_fits(a, L1LS_SPLIT_BF16)) {
-            switch (T) {
-            case 1: return launch_mfma_one<1, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
-            case 2: return launch_mfma_one<2, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
-            case 3: return launch_mfma_one<3, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
-            case 4: return launch_mfma_one<4, 4, true, L1LS_SPLIT_BF16, 4>(a, max_groups, s);
-            default: break;
-            }
+        if (alt != 0) return false;
+        if (slice_blocks_for(l) == 8 && mfma_lds_fits(probe, L1LS_SPLIT_BF16) && T <= 4) {
+            r = IterVariant{kVarMfma, T, 4, 1, L1LS_SPLIT_BF16, 4, waves, 0};
+        } else {
+            const int zb = zblocks_for(n);
+            r = IterVariant{kVarEmbedded, zb, slice_blocks_for(l), fista_a_fits_lds(n, l_pad, waves, zb) ? 1 : 0,
+                            L1LS_SPLIT_BF16, 4, waves, 0};
         }
-        return launch_prec<L1LS_SPLIT_BF16>(a, max_groups, s);
+        *v = r;
+        return true;
     }
-    switch (T) {
-    case 1: return launch_mfma_t<1>(a, max_groups, s);
-    case 2: return launch_mfma_t<2>(a, max_groups, s);
-    case 3: return launch_mfma_t<3>(a, max_groups, s);
-    case 4: return launch_mfma_t<4>(a, max_groups, s);
-    default: return launch_prec<L1LS_FP32>(a, max_groups, s);
+    bool kb2 = T <= 2 && slice_blocks_for(l) == 8;
+    if (alt == 2) {
+        if (!(T <= 2 && slice_blocks_for(l) == 8)) return false;
+        kb2 = !kb2;
+    }
+    if (kb2) {
+        FistaArgs b = probe;
+        b.waves = l_pad / 32;
+        r = IterVariant{kVarMfma, T, 2, mfma_lds_fits(b, L1LS_FP32) ? 1 : 0, L1LS_FP32, 8, b.waves, 0};
+    } else {
+        r = IterVariant{kVarMfma, T, slice_blocks_for(l) == 8 ? 4 : 8, mfma_lds_fits(probe, L1LS_FP32) ? 1 : 0,
+                        L1LS_FP32, 4, waves, 0};
+    }
+    if (alt == 1) {
+        if (!r.alds) return false;  // the LDS copy does not fit: no alternative placement
+        r.alds = 0;
+    }
+    *v = r;
+    return true;
+}
+
+size_t iter_variant_lds(const IterVariant &v, int n, int l)
+{
+    if (v.family == kVarWave) return fista_wave_lds(n, l);
+    if (v.family == kVarMfma) return fista_mfma_lds_bytes(n, lpad_for(l), v.waves, v.alds != 0, v.prec);
+    return fista_lds_bytes(n, lpad_for(l), v.waves, v.T, v.alds != 0);
+}
+
+template <int T, int PREC>
+static hipError_t launch_mfma_t(const StackTable &t, const IterVariant &v, hipStream_t s)
+{
+    if constexpr (PREC == L1LS_SPLIT_BF16) {
+        return launch_mfma_one<T, 4, true, L1LS_SPLIT_BF16, 4>(t, v.waves, s);
+    } else {
+        if constexpr (T <= 2) {
+            if (v.KB == 2)
+                return v.alds ? launch_mfma_one<T, 2, true, L1LS_FP32, 8>(t, v.waves, s)
+                              : launch_mfma_one<T, 2, false, L1LS_FP32, 8>(t, v.waves, s);
+        }
+        if (v.KB == 4)
+            return v.alds ? launch_mfma_one<T, 4, true, L1LS_FP32, 4>(t, v.waves, s)
+                          : launch_mfma_one<T, 4, false, L1LS_FP32, 4>(t, v.waves, s);
+        if (v.KB == 8)
+            return v.alds ? launch_mfma_one<T, 8, true, L1LS_FP32, 4>(t, v.waves, s)
+                          : launch_mfma_one<T, 8, false, L1LS_FP32, 4>(t, v.waves, s);
+        return hipErrorInvalidValue;
+    }
+}
+
+// One launch for the stacks of a table that all run variant v (the
+// real-embedded kernel takes one stack per launch).
+hipError_t launch_iteration_table(const StackTable &t, const IterVariant &v, hipStream_t s)
+{
+    if (v.family == kVarWave) return launch_wave_table(t, v.nc, s);
+    if (v.family == kVarEmbedded) {
+        for (int i = 0; i < t.count; ++i) {
+            if (t.d[i].p <= 0) continue;
+            const FistaArgs a = fista_args_for(t.d[i], t.o);
+            if (a.warm) return hipErrorNotSupported;
+            const hipError_t e = launch_prec<L1LS_SPLIT_BF16>(a, 0, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const bool bf = v.prec == L1LS_SPLIT_BF16;
+    switch (v.T) {
+    case 1: return bf ? launch_mfma_t<1, L1LS_SPLIT_BF16>(t, v, s) : launch_mfma_t<1, L1LS_FP32>(t, v, s);
+    case 2: return bf ? launch_mfma_t<2, L1LS_SPLIT_BF16>(t, v, s) : launch_mfma_t<2, L1LS_FP32>(t, v, s);
+    case 3: return bf ? launch_mfma_t<3, L1LS_SPLIT_BF16>(t, v, s) : launch_mfma_t<3, L1LS_FP32>(t, v, s);
+    case 4: return bf ? launch_mfma_t<4, L1LS_SPLIT_BF16>(t, v, s) : launch_mfma_t<4, L1LS_FP32>(t, v, s);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -152,7 +152,7 @@ __host__ __device__ inline size_t fm_bf_planes_bytes(int rows, int l_pad)
 }
 
 template <int T, int KB, bool ALDS, int PREC, int WMAX>
-__global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a)
+__device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 {
     static_assert(PREC == L1LS_FP32 || ALDS, "split-BF16 stages its A planes in LDS");
     constexpr bool BF = PREC == L1LS_SPLIT_BF16;
@@ -801,11 +801,35 @@ __global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const FistaArgs a
 
 
 
+// The stacks of a table one after another: a workgroup takes 16-pixel tiles of a
+// stack from that stack's queue until it is empty and its own tile has drained,
+// then stages the next stack's A.  Every stack of the table has this tiling
+// (same T, KB and waves, hence the same padded L and LDS size).
 template <int T, int KB, bool ALDS, int PREC, int WMAX>
-hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s)
+__global__ void __launch_bounds__(64 * WMAX) fista_mfma_kernel(const StackTable t)
 {
-    if (a.waves < 1 || a.waves > WMAX || a.waves * 16 * KB != a.l_pad) return hipErrorInvalidConfiguration;
-    const size_t lds = fista_mfma_lds_bytes(a.n, a.l_pad, a.waves, ALDS, PREC);
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        FistaArgs a = fista_args_for(t.d[i], t.o);
+        a.waves = blockDim.x / 64;
+        fista_mfma_stack<T, KB, ALDS, PREC, WMAX>(a);
+        __syncthreads();
+    }
+}
+
+template <int T, int KB, bool ALDS, int PREC, int WMAX>
+hipError_t launch_mfma_one(const StackTable &t, int waves, hipStream_t s)
+{
+    if (waves < 1 || waves > WMAX) return hipErrorInvalidConfiguration;
+    int64_t need = 0;
+    for (int i = 0; i < t.count; ++i) {
+        const StackDesc &d = t.d[i];
+        if (d.p <= 0) continue;
+        if (waves * 16 * KB != lpad_for(d.l) || rows_pad_for(d.n) != 16 * T) return hipErrorInvalidConfiguration;
+        need += (d.p + kTile - 1) / kTile;
+    }
+    if (need == 0) return hipSuccess;
+    const size_t lds = fista_mfma_lds_bytes(16 * T, waves * 16 * KB, waves, ALDS, PREC);
     auto kern = fista_mfma_kernel<T, KB, ALDS, PREC, WMAX>;
     static bool attr_done = false;  // per instantiation
     if (!attr_done) {
@@ -814,18 +838,16 @@ hipError_t launch_mfma_one(const FistaArgs &a, int max_groups, hipStream_t s)
         attr_done = true;
     }
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * a.waves, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * waves, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t groups = (int64_t)per_cu * cus;
-    const int64_t need = (a.p + kTile - 1) / kTile;
     if (groups > need) groups = need;
-    if (max_groups > 0 && groups > max_groups) groups = max_groups;
     if (groups < 1) groups = 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64 * a.waves), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64 * waves), lds, s, t);
     return hipGetLastError();
 }
 

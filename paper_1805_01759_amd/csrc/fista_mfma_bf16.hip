@@ -4,8 +4,8 @@
 
 namespace l1ls {
 size_t fm_bf_planes_bytes_host(int rows, int l_pad) { return fm_bf_planes_bytes(rows, l_pad); }
-template hipError_t launch_mfma_one<1, 4, true, L1LS_SPLIT_BF16, 4>(const FistaArgs &, int, hipStream_t);
-template hipError_t launch_mfma_one<2, 4, true, L1LS_SPLIT_BF16, 4>(const FistaArgs &, int, hipStream_t);
-template hipError_t launch_mfma_one<3, 4, true, L1LS_SPLIT_BF16, 4>(const FistaArgs &, int, hipStream_t);
-template hipError_t launch_mfma_one<4, 4, true, L1LS_SPLIT_BF16, 4>(const FistaArgs &, int, hipStream_t);
+template hipError_t launch_mfma_one<1, 4, true, L1LS_SPLIT_BF16, 4>(const StackTable &, int, hipStream_t);
+template hipError_t launch_mfma_one<2, 4, true, L1LS_SPLIT_BF16, 4>(const StackTable &, int, hipStream_t);
+template hipError_t launch_mfma_one<3, 4, true, L1LS_SPLIT_BF16, 4>(const StackTable &, int, hipStream_t);
+template hipError_t launch_mfma_one<4, 4, true, L1LS_SPLIT_BF16, 4>(const StackTable &, int, hipStream_t);
 }  // namespace l1ls

@@ -3,8 +3,8 @@
 #include "fista_mfma.h"
 
 namespace l1ls {
-template hipError_t launch_mfma_one<1, 2, true, L1LS_FP32, 8>(const FistaArgs &, int, hipStream_t);
-template hipError_t launch_mfma_one<1, 2, false, L1LS_FP32, 8>(const FistaArgs &, int, hipStream_t);
-template hipError_t launch_mfma_one<2, 2, true, L1LS_FP32, 8>(const FistaArgs &, int, hipStream_t);
-template hipError_t launch_mfma_one<2, 2, false, L1LS_FP32, 8>(const FistaArgs &, int, hipStream_t);
+template hipError_t launch_mfma_one<1, 2, true, L1LS_FP32, 8>(const StackTable &, int, hipStream_t);
+template hipError_t launch_mfma_one<1, 2, false, L1LS_FP32, 8>(const StackTable &, int, hipStream_t);
+template hipError_t launch_mfma_one<2, 2, true, L1LS_FP32, 8>(const StackTable &, int, hipStream_t);
+template hipError_t launch_mfma_one<2, 2, false, L1LS_FP32, 8>(const StackTable &, int, hipStream_t);
 }  // namespace l1ls

@@ -10,6 +10,8 @@
 //   r_{k+1} = r(y) + w,  G_{k+1} = 2 A^H r_{k+1}
 // One wave per pixel; A is read from the packed workspace copies (L2-resident:
 // it is shared by every pixel).
+#include <algorithm>
+
 #include "l1ls_internal.h"
 
 namespace l1ls {
@@ -47,7 +49,7 @@ __device__ __forceinline__ void cprox_w(float vr, float vi, float tau, float &o_
 // instantiated count); d, the residuals and A d sit in LDS for the row-wise
 // forward product, so a pixel needs (l_pad + 3 N) x 8 bytes of LDS.
 template <int NC>
-__global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
+__device__ __forceinline__ void fista_wave_stack(const FistaArgs &a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
@@ -284,8 +286,18 @@ __global__ void __launch_bounds__(64) fista_wave_kernel(const FistaArgs a)
     }
 }
 
+// The stacks of a table one after another (pixels from each stack's queue).
+template <int NC>
+__global__ void __launch_bounds__(64) fista_wave_kernel(const StackTable t)
+{
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        fista_wave_stack<NC>(fista_args_for(t.d[i], t.o));
+    }
+}
+
 // instantiated chunk counts (64 bins each) and the one used for l
-static int wave_chunks(int l)
+int wave_chunks(int l)
 {
     const int c = (l + 63) / 64;
     const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16};
@@ -297,9 +309,17 @@ static int wave_chunks(int l)
 size_t fista_wave_lds(int n, int l) { return (size_t)(64 * wave_chunks(l) + 3 * n) * sizeof(float2); }
 
 template <int NC>
-static hipError_t launch_wave_nc(const FistaArgs &a, hipStream_t s)
+static hipError_t launch_wave_nc(const StackTable &t, hipStream_t s)
 {
-    const size_t lds = fista_wave_lds(a.n, a.l);
+    size_t lds = 0;
+    int64_t need = 0;
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        if (wave_chunks(t.d[i].l) != NC) return hipErrorInvalidConfiguration;
+        lds = std::max(lds, fista_wave_lds(t.d[i].n, t.d[i].l));
+        need += t.d[i].p;
+    }
+    if (need == 0) return hipSuccess;
     auto kern = fista_wave_kernel<NC>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds);
@@ -309,23 +329,23 @@ static hipError_t launch_wave_nc(const FistaArgs &a, hipStream_t s)
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t groups = (int64_t)per_cu * cus;
-    if (groups > a.p) groups = a.p;
+    if (groups > need) groups = need;
     if (groups < 1) groups = 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64), lds, s, t);
     return hipGetLastError();
 }
 
-hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s)
+hipError_t launch_wave_table(const StackTable &t, int nc, hipStream_t s)
 {
-    switch (wave_chunks(a.l)) {
-    case 1: return launch_wave_nc<1>(a, s);
-    case 2: return launch_wave_nc<2>(a, s);
-    case 3: return launch_wave_nc<3>(a, s);
-    case 4: return launch_wave_nc<4>(a, s);
-    case 6: return launch_wave_nc<6>(a, s);
-    case 8: return launch_wave_nc<8>(a, s);
-    case 12: return launch_wave_nc<12>(a, s);
-    case 16: return launch_wave_nc<16>(a, s);
+    switch (nc) {
+    case 1: return launch_wave_nc<1>(t, s);
+    case 2: return launch_wave_nc<2>(t, s);
+    case 3: return launch_wave_nc<3>(t, s);
+    case 4: return launch_wave_nc<4>(t, s);
+    case 6: return launch_wave_nc<6>(t, s);
+    case 8: return launch_wave_nc<8>(t, s);
+    case 12: return launch_wave_nc<12>(t, s);
+    case 16: return launch_wave_nc<16>(t, s);
     default: return hipErrorInvalidValue;
     }
 }

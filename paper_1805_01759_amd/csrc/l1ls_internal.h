@@ -116,27 +116,225 @@ struct PolishArgsDev {
 // each holds A^H b of its current pixel in the workspace.
 constexpr int kMaxRefineGroups = 3072;
 
-// Workspace layout for one stack.
+// Tiling helpers (host and device): KB MFMA row blocks of 16 unknowns per wave
+// slice, W waves, l padded to 8 KB W, 2N real rows in 16-row blocks, N padded to 16.
+__host__ __device__ inline int slice_blocks_for(int l) { return l <= 256 ? 8 : 16; }
+__host__ __device__ inline int waves_for(int l)
+{
+    const int slice = 8 * slice_blocks_for(l);
+    return (l + slice - 1) / slice;
+}
+__host__ __device__ inline int lpad_for(int l) { return waves_for(l) * 8 * slice_blocks_for(l); }
+__host__ __device__ inline int zblocks_for(int n) { return (2 * n + 15) / 16; }
+__host__ __device__ inline int rows_pad_for(int n) { return 16 * ((n + 15) / 16); }
+__host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace layout for one stack (byte offsets; every region 256-byte aligned).
 struct StackWorkspace {
     size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid,
         overflow, hgram, cbuf, total;
 };
-StackWorkspace stack_workspace_layout(int n, int l, int64_t p);
+__host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
+{
+    StackWorkspace w;
+    const int l_pad = lpad_for(l);
+    size_t off = 0;
+    w.a_packed = off;
+    off = ws_align(off + (size_t)rows_pad_for(n) * l_pad * sizeof(float2));
+    w.a_trans = off;
+    off = ws_align(off + (size_t)l_pad * n * sizeof(float2));
+    w.gram = off;
+    off = ws_align(off + (size_t)n * n * sizeof(double2));
+    w.consts = off;
+    off = ws_align(off + sizeof(StackConsts));
+    w.queue = off;
+    off = ws_align(off + 8 * sizeof(uint32_t));
+    w.work = off;
+    off = ws_align(off + 4 * sizeof(unsigned long long));
+    w.status = off;
+    off = ws_align(off + (size_t)p * sizeof(uint32_t));
+    w.iters = off;
+    off = ws_align(off + (size_t)p * sizeof(int32_t));
+    w.kkt32 = off;
+    off = ws_align(off + (size_t)p * sizeof(float));
+    w.polish_list = off;
+    off = ws_align(off + (size_t)p * sizeof(int32_t));
+    w.blocks = off;
+    off = ws_align(off + (size_t)kMaxBlocks * sizeof(BlockConsts));
+    w.resid = off;
+    off = ws_align(off + (size_t)p * n * sizeof(float2));
+    w.overflow = off;
+    off = ws_align(off + (size_t)p * sizeof(int32_t));
+    // the refinement's bin Gram A^H A and the A^H b of its workgroups' pixels
+    w.hgram = off;
+    off = ws_align(off + (size_t)l * l * sizeof(double2));
+    w.cbuf = off;
+    const int64_t groups = p < kMaxRefineGroups ? p : kMaxRefineGroups;
+    off = ws_align(off + (size_t)groups * l * sizeof(double2));
+    w.total = off;
+    return w;
+}
 
-int slice_blocks_for(int l);   // KB
-int waves_for(int l);          // W
-int lpad_for(int l);           // 8 KB W
-int zblocks_for(int n);
-int rows_pad_for(int n);       // rows of the packed A: N rounded up to 16
+// ---------------------------------------------------------------------------
+// Stack tables.  Every kernel of a solve takes up to kMaxStacksPerLaunch stacks
+// (a single solve is a table of one) and sweeps them in table order: persistent
+// workgroups take pixels from a stack's own queue until it is empty, then move
+// on to the next stack (restaging that stack's A), so a batch of stacks of one
+// tile class is one launch.  The table travels as the kernel argument.
+struct StackDesc {
+    const float2 *A;          // caller's A (n x l, row-major)
+    const float2 *B;          // p x n
+    const float *lambda;
+    float2 *X;                // p x l
+    char *ws;                 // the stack's workspace (stack_workspace_layout)
+    int32_t *iters;           // diagnostics (any may be null)
+    float *kkt;
+    float *objective;
+    uint32_t *status;
+    int32_t *nnz;
+    int64_t p, lambda_stride;
+    int32_t n, l;
+    int32_t keep_residual;    // the stack's iteration kernel writes the residual of each retired pixel
+    int32_t pad;
+};
+struct SolveOpts {
+    int32_t fista_cap;        // retire unsolved pixels after this many iterations
+    float tol, c_alpha;
+    int32_t backtracking, monotone, polish, warm;
+    int32_t pad;
+};
+constexpr int kMaxStacksPerLaunch = 32;
+struct StackTable {
+    int32_t count;
+    SolveOpts o;
+    StackDesc d[kMaxStacksPerLaunch];
+};
+static_assert(sizeof(StackTable) <= 4000, "a stack table travels as a kernel argument");
 
-hipError_t launch_setup(int n, int l, int l_pad, const float2 *A, float2 *Ap, float2 *At, double2 *gram,
-                        StackConsts *consts, uint32_t *queue, unsigned long long *work,
-                        hipStream_t s);
-hipError_t launch_setup_bin_gram(int n, int l, const float2 *A, double2 *H, hipStream_t s);
-hipError_t launch_fista(const FistaArgs &a, int precision, int max_groups, hipStream_t s,
-                        bool *keeps_residual = nullptr);
-hipError_t launch_fista_wave(const FistaArgs &a, hipStream_t s);
-bool fista_split_kernel(const FistaArgs &a, int precision);
+// Per-stack argument blocks of the kernels, from a table entry (host and device).
+__host__ __device__ inline FistaArgs fista_args_for(const StackDesc &d, const SolveOpts &o)
+{
+    const StackWorkspace lay = stack_workspace_layout(d.n, d.l, d.p);
+    FistaArgs fa;
+    fa.n = d.n;
+    fa.l = d.l;
+    fa.l_pad = lpad_for(d.l);
+    fa.waves = waves_for(d.l);
+    fa.p = d.p;
+    fa.A = (const float2 *)(d.ws + lay.a_packed);
+    fa.At = (const float2 *)(d.ws + lay.a_trans);
+    fa.B = d.B;
+    fa.lambda = d.lambda;
+    fa.lambda_stride = d.lambda_stride;
+    fa.X = d.X;
+    fa.iters = (int32_t *)(d.ws + lay.iters);
+    fa.kkt32 = (float *)(d.ws + lay.kkt32);
+    fa.status = (uint32_t *)(d.ws + lay.status);
+    fa.consts = (const StackConsts *)(d.ws + lay.consts);
+    fa.queue = (uint32_t *)(d.ws + lay.queue);
+    fa.polish_count = fa.queue + 1;
+    fa.polish_list = (int32_t *)(d.ws + lay.polish_list);
+    fa.work = (unsigned long long *)(d.ws + lay.work);
+    fa.R = d.keep_residual ? (float2 *)(d.ws + lay.resid) : nullptr;
+    fa.fista_cap = o.fista_cap;
+    fa.tol = o.tol;
+    fa.c_alpha = o.c_alpha;
+    fa.backtracking = o.backtracking;
+    fa.monotone = o.monotone;
+    fa.polish = o.polish;
+    fa.warm = o.warm;
+    return fa;
+}
+
+// wide: the 32-slot pass over the pixels the 16-slot pass listed
+__host__ __device__ inline PolishArgsDev polish_args_for(const StackDesc &d, const SolveOpts &o, bool wide)
+{
+    const StackWorkspace lay = stack_workspace_layout(d.n, d.l, d.p);
+    uint32_t *queue = (uint32_t *)(d.ws + lay.queue);
+    PolishArgsDev pa;
+    pa.n = d.n;
+    pa.l = d.l;
+    pa.l_pad = lpad_for(d.l);
+    pa.A = (const float2 *)(d.ws + lay.a_packed);
+    pa.B = d.B;
+    pa.lambda = d.lambda;
+    pa.lambda_stride = d.lambda_stride;
+    pa.X = d.X;
+    pa.consts = (const StackConsts *)(d.ws + lay.consts);
+    pa.count = wide ? queue + 3 : queue + 1;
+    pa.next = wide ? queue + 4 : queue + 2;
+    pa.list = wide ? (const int32_t *)(d.ws + lay.overflow) : (const int32_t *)(d.ws + lay.polish_list);
+    pa.R = (!wide && d.keep_residual) ? (const float2 *)(d.ws + lay.resid) : nullptr;
+    pa.overflow = wide ? nullptr : (int32_t *)(d.ws + lay.overflow);
+    pa.overflow_count = wide ? nullptr : queue + 3;
+    pa.status = (uint32_t *)(d.ws + lay.status);
+    pa.work = (unsigned long long *)(d.ws + lay.work);
+    pa.H = (const double2 *)(d.ws + lay.hgram);
+    pa.cbuf = (double2 *)(d.ws + lay.cbuf);
+    pa.rounds = 64;
+    pa.mode = o.polish;
+    pa.tol = o.tol;
+    pa.max_groups = (int)(d.p < kMaxRefineGroups ? d.p : kMaxRefineGroups);
+    return pa;
+}
+
+__host__ __device__ inline CertifyArgs certify_args_for(const StackDesc &d, const SolveOpts &o)
+{
+    const StackWorkspace lay = stack_workspace_layout(d.n, d.l, d.p);
+    CertifyArgs ca;
+    ca.n = d.n;
+    ca.l = d.l;
+    ca.l_pad = lpad_for(d.l);
+    ca.p = d.p;
+    ca.A = (const float2 *)(d.ws + lay.a_packed);
+    ca.B = d.B;
+    ca.lambda = d.lambda;
+    ca.lambda_stride = d.lambda_stride;
+    ca.X = d.X;
+    ca.iters_in = (const int32_t *)(d.ws + lay.iters);
+    ca.status_in = (const uint32_t *)(d.ws + lay.status);
+    ca.consts = (const StackConsts *)(d.ws + lay.consts);
+    ca.tol = o.tol;
+    ca.polish = o.polish;
+    ca.iters = d.iters;
+    ca.kkt = d.kkt;
+    ca.objective = d.objective;
+    ca.status = d.status;
+    ca.nnz = d.nnz;
+    return ca;
+}
+
+// Launches over a stack table (every entry with p > 0).
+hipError_t launch_setup_table(const StackTable &t, bool bin_gram, hipStream_t s);
+hipError_t launch_certify_table(const StackTable &t, hipStream_t s);
+hipError_t launch_polish_table(const StackTable &t, hipStream_t s);       // 16 slots
+hipError_t launch_polish_wide_table(const StackTable &t, hipStream_t s);  // 32 slots
+
+// The iteration kernel that runs a stack: the split re/im MFMA tile (T row
+// blocks, KB unknown blocks per wave, A staged in LDS or read from L2, up to
+// WMAX waves of which `waves` run), or the wave-per-pixel kernel (NC chunks).
+struct IterVariant {
+    int family;   // kVarMfma, kVarWave, kVarEmbedded (real-embedded, one stack per launch)
+    int T, KB, alds, prec, wmax, waves, nc;
+    bool operator==(const IterVariant &o) const
+    {
+        return family == o.family && T == o.T && KB == o.KB && alds == o.alds && prec == o.prec &&
+               wmax == o.wmax && waves == o.waves && nc == o.nc;
+    }
+};
+enum { kVarMfma = 1, kVarWave = 2, kVarEmbedded = 3 };
+// The default variant for a shape and precision (kMfma: the MFMA families, kWave:
+// the wave kernel); `alt` selects an alternative tiling for the autotuner
+// (0 default, 1 the other A placement, 2 the other unknowns-per-wave split);
+// returns false when the alternative does not exist.
+bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant *v);
+// LDS bytes of a variant for one stack, and the launch over a table whose
+// stacks all run that variant.
+size_t iter_variant_lds(const IterVariant &v, int n, int l);
+hipError_t launch_iteration_table(const StackTable &t, const IterVariant &v, hipStream_t s);
+
+
+
 hipError_t launch_setup_blocks(int n, int l, int J, const float2 *A, BlockConsts *bc, hipStream_t s);
 hipError_t launch_fista_blocks(const BlocksArgs &ba, hipStream_t s);
 size_t fista_blocks_lds(int n, int l_pad, int J);
@@ -149,11 +347,16 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
                         const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
                         l1ls_c32 *X, const l1ls_diag *diag, void *ws, size_t ws_bytes,
                         hipStream_t s, int choice, int blocks = 0,
-                        const double *draws = nullptr);
+                        const double *draws = nullptr, int alt = 0);
+l1ls_status check_options(const l1ls_options *o);
+l1ls_status check_stack(int32_t n, int32_t l, int64_t p, const void *A, const void *B, const float *lambda,
+                        int64_t lambda_stride, const void *X, const void *ws, size_t ws_bytes);
+l1ls_status stack_variant(int32_t n, int32_t l, const l1ls_options *opt, int choice, int alt, IterVariant *v);
+StackDesc stack_desc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B, const float *lambda,
+                     int64_t lambda_stride, l1ls_c32 *X, const l1ls_diag *diag, void *ws, const IterVariant &v);
+l1ls_status run_stacks(const StackDesc *d, const IterVariant *var, int count, const l1ls_options *opt,
+                       hipStream_t s);
 l1ls_status set_error(l1ls_status st, const char *fmt, ...);
-hipError_t launch_certify(const CertifyArgs &a, hipStream_t s);
-hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s);       // 16 slots
-hipError_t launch_polish_wide(const PolishArgsDev &a, int groups, hipStream_t s);  // 32 slots
 size_t unrolled_tape_bytes(int n, int l, int64_t p, int K, int ckpt);
 size_t unrolled_bwd_ws_bytes(int n, int l, int64_t p, int K, int ckpt);
 hipError_t launch_unrolled_forward(int n, int l, int64_t p, const float *xi, const float *s,

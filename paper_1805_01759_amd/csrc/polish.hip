@@ -632,7 +632,7 @@ __device__ bool newton_regs(PolishShared &sh, int m2, double mu, double &d)
     return true;
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) polish_kernel(const PolishArgsDev a)
+__device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
 {
     __shared__ PolishShared sh;
     extern __shared__ __align__(16) unsigned char dyn[];
@@ -1134,6 +1134,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
     if (lane == 0 && fl32) atomicAdd(&a.work[3], fl32);
 }
 
+// The stacks of a table one after another: each workgroup takes listed pixels
+// of a stack from that stack's counter, then moves on.  A workgroup beyond a
+// stack's number of A^H b buffers skips that stack (the others cover it).
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) polish_kernel(const StackTable t)
+{
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        const PolishArgsDev a = polish_args_for(t.d[i], t.o, kMaxSupp == 32);
+        if ((int)blockIdx.x >= a.max_groups) continue;
+        polish_stack(a);
+        __syncthreads();
+    }
+}
+
 size_t polish_lds_bytes(int n, int l_pad)
 {
     return (size_t)2 * n * sizeof(double2) + (size_t)n * sizeof(float2) +
@@ -1141,19 +1155,27 @@ size_t polish_lds_bytes(int n, int l_pad)
            (size_t)n * kMaxSupp * sizeof(float2);
 }
 
-hipError_t launch_polish(const PolishArgsDev &a, int groups, hipStream_t s)
+hipError_t launch_polish_table(const StackTable &t, hipStream_t s)
 {
-    const size_t dyn = polish_lds_bytes(a.n, a.l_pad);
+    size_t dyn = 0;
+    int want = 0;
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        dyn = dyn > polish_lds_bytes(t.d[i].n, lpad_for(t.d[i].l)) ? dyn : polish_lds_bytes(t.d[i].n, lpad_for(t.d[i].l));
+        const int mg = (int)(t.d[i].p < kMaxRefineGroups ? t.d[i].p : kMaxRefineGroups);
+        want = want > mg ? want : mg;
+    }
+    if (want == 0) return hipSuccess;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, polish_kernel, 64, dyn);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int g = per_cu > 0 ? per_cu * cus : groups;
-    if (g > a.max_groups) g = a.max_groups;  // one A^H b buffer per workgroup
+    int g = per_cu > 0 ? per_cu * cus : cus * 4;
+    if (g > want) g = want;  // one A^H b buffer per workgroup
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(polish_kernel, dim3(g), dim3(64), dyn, s, a);
+    hipLaunchKernelGGL(polish_kernel, dim3(g), dim3(64), dyn, s, t);
     return hipGetLastError();
 }
 

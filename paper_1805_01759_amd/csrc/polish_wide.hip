@@ -4,5 +4,6 @@
 #define L1LS_POLISH_SUPP 32
 #define polish_kernel polish_kernel_wide
 #define polish_lds_bytes polish_lds_bytes_wide
-#define launch_polish launch_polish_wide
+#define launch_polish_table launch_polish_wide_table
+#define polish_stack polish_stack_wide
 #include "polish.hip"

@@ -94,7 +94,7 @@ def test_close_pairs_full_size(dev, orc, prec, bar, floor):
     del B
     Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
     X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, precision=prec, fp64_polish=bench.ACCURACY_MODE,
-                     polish_after=bench.POLISH_AFTER)
+                     polish_after=bench.polish_after_for("pairs"))
     p = B32.shape[0]
     idx = np.arange(11, p, p // 192)
     _check_sampled(orc, A32, B32, l32, X, d, idx, bar, pass_floor=floor)
