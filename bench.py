@@ -50,11 +50,12 @@ SUPERRES_REALISATIONS = 5000
 
 # sources of each timed kernel; a traffic record is used only while they are unchanged
 KERNEL_SOURCES = {
-    "fista_mfma_kernel": ("fista_mfma.h", "fista.hip"),
-    "fista_mfma_kernel_bf16": ("fista_mfma.h", "fista.hip"),
-    "fista_kernel": ("fista_impl.h", "fista.hip"),
-    "polish_kernel": ("polish.hip", "wave_reduce.h"),
-    "certify_kernel": ("certify.hip", "wave_reduce.h"),
+    "fista_mfma_kernel": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
+    "fista_mfma_kernel_bf16": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
+    "fista_kernel": ("fista_impl.h", "fista.hip", "l1ls_internal.h"),
+    "fista_wave_kernel": ("fista_wave.hip", "l1ls_internal.h"),
+    "polish_kernel": ("polish.hip", "wave_reduce.h", "l1ls_internal.h"),
+    "certify_kernel": ("certify.hip", "wave_reduce.h", "l1ls_internal.h"),
 }
 PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
 PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s
@@ -400,7 +401,11 @@ def rooflines(r, n, l, prec, workload, polish):
     """Roofline objects of the iteration and refinement kernels of one run."""
     avg_s = r["avg_s"]
     if n <= 64 and l <= 512:
-        it_kernel = "fista_mfma_kernel" if prec == "fp32" else "fista_mfma_kernel_bf16"
+        if prec == "fp32":
+            it_kernel = "fista_mfma_kernel"
+        else:
+            # split-BF16 with 256 < L runs the real-embedded kernel (its A planes do not fit LDS)
+            it_kernel = "fista_mfma_kernel_bf16" if l <= 256 else "fista_kernel"
     else:
         it_kernel = "fista_wave_kernel"
     # iteration kernel: algorithmic flops = (forward + adjoint products) x 8 N L

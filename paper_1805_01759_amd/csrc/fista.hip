@@ -278,6 +278,8 @@ size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precisi
     off += (size_t)waves * 2 * T * 64 * 16;
     off += (size_t)waves * 16 * 16;
     off += 16;
+    // 128 unknowns a wave: G_{k-1} of the tile's 16 pixels in LDS (float2 each)
+    if (l_pad / (16 * waves) >= 8) off += (size_t)16 * l_pad * sizeof(float2);
     return off;
 }
 

@@ -180,6 +180,12 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
     f4 *sPS = reinterpret_cast<f4 *>(smem + off);   // [W][16] per-slot partial scalars
     off += (size_t)W * 16 * sizeof(f4);
     uint32_t *sQ = reinterpret_cast<uint32_t *>(smem + off);
+    off += 16;
+    // LEAN (128 unknowns a wave): G_{k-1} lives in LDS, one float2 per lane and
+    // (block, q) of each wave, and x-bar is recomputed at the acceptance instead
+    // of kept; the state then fits the registers of one wave per SIMD
+    constexpr bool LEAN = KB >= 8;
+    float2 *sGp = reinterpret_cast<float2 *>(smem + off) + (size_t)w * KB * 4 * 64 + lane;
 
     fm::AView Av;
     if constexpr (BF) {
@@ -226,9 +232,14 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 #pragma unroll
     for (int b = 0; b < KB; ++b)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            Xr[b][q] = Xi[b][q] = Xpr[b][q] = Xpi[b][q] = Gr[b][q] = Gi[b][q] = Gpr[b][q] =
-                Gpi[b][q] = XBr[b][q] = XBi[b][q] = 0.0f;
+        for (int q = 0; q < 4; ++q) {
+            Xr[b][q] = Xi[b][q] = Xpr[b][q] = Xpi[b][q] = Gr[b][q] = Gi[b][q] = 0.0f;
+            if constexpr (LEAN) {
+                sGp[(b * 4 + q) * 64] = make_float2(0.0f, 0.0f);
+            } else {
+                Gpr[b][q] = Gpi[b][q] = XBr[b][q] = XBi[b][q] = 0.0f;
+            }
+        }
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -286,8 +297,12 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
                 Xi[b][q] = fresh ? 0.0f : Xi[b][q];
                 Xpr[b][q] = fresh ? 0.0f : Xpr[b][q];
                 Xpi[b][q] = fresh ? 0.0f : Xpi[b][q];
-                Gpr[b][q] = fresh ? 0.0f : Gpr[b][q];
-                Gpi[b][q] = fresh ? 0.0f : Gpi[b][q];
+                if constexpr (LEAN) {
+                    if (fresh) sGp[(b * 4 + q) * 64] = make_float2(0.0f, 0.0f);
+                } else {
+                    Gpr[b][q] = fresh ? 0.0f : Gpr[b][q];
+                    Gpi[b][q] = fresh ? 0.0f : Gpi[b][q];
+                }
             }
         float bb = 0.0f;
         const float2 *Bp = a.B + (size_t)(fresh ? pix : 0) * n;
@@ -514,12 +529,23 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     float y_r, y_i, xb_r, xb_i, axb;
+                    float gp_r, gp_i;
+                    if constexpr (LEAN) {
+                        const float2 g2 = sGp[(b * 4 + q) * 64];
+                        gp_r = g2.x;
+                        gp_i = g2.y;
+                    } else {
+                        gp_r = Gpr[b][q];
+                        gp_i = Gpi[b][q];
+                    }
                     fm::trial_one(Xr[b][q], Xi[b][q], Xpr[b][q], Xpi[b][q], Gr[b][q], Gi[b][q],
-                                  Gpr[b][q], Gpi[b][q], beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
+                                  gp_r, gp_i, beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
                     dr[b][q] = xb_r - y_r;
                     di[b][q] = xb_i - y_i;
-                    XBr[b][q] = xb_r;
-                    XBi[b][q] = xb_i;
+                    if constexpr (!LEAN) {
+                        XBr[b][q] = xb_r;
+                        XBi[b][q] = xb_i;
+                    }
                     d2 = fmaf(dr[b][q], dr[b][q], fmaf(di[b][q], di[b][q], d2));
                     s1 += axb - __builtin_amdgcn_sqrtf(fmaf(Xr[b][q], Xr[b][q], Xi[b][q] * Xi[b][q]));
                 }
@@ -693,13 +719,16 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
                     Wr[t] *= c;
                     Wi[t] *= c;
                 }
+                if constexpr (!LEAN) {
+                    // (LEAN recomputes x-bar at the acceptance with the final step)
 #pragma unroll
-                for (int b = 0; b < KB; ++b)
+                    for (int b = 0; b < KB; ++b)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        XBr[b][q] *= c;
-                        XBi[b][q] *= c;
-                    }
+                        for (int q = 0; q < 4; ++q) {
+                            XBr[b][q] *= c;
+                            XBi[b][q] *= c;
+                        }
+                }
                 w2 *= c * c;
                 d2s *= c * c;
                 l1 *= c;
@@ -757,15 +786,33 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
             for (int b = 0; b < KB; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if (live) {
-                        Xpr[b][q] = Xr[b][q];
-                        Xpi[b][q] = Xi[b][q];
-                        Gpr[b][q] = Gr[b][q];
-                        Gpi[b][q] = Gi[b][q];
-                    }
-                    if (accept) {
-                        Xr[b][q] = XBr[b][q];
-                        Xi[b][q] = XBi[b][q];
+                    if constexpr (LEAN) {
+                        // x-bar of the last trial, recomputed from the same inputs (the
+                        // jump of the first iteration: at its final step)
+                        const float2 g2 = sGp[(b * 4 + q) * 64];
+                        float y_r, y_i, xb_r, xb_i, axb;
+                        fm::trial_one(Xr[b][q], Xi[b][q], Xpr[b][q], Xpi[b][q], Gr[b][q], Gi[b][q], g2.x,
+                                      g2.y, beta, alpha, alpha * lam, y_r, y_i, xb_r, xb_i, axb);
+                        if (live) {
+                            Xpr[b][q] = Xr[b][q];
+                            Xpi[b][q] = Xi[b][q];
+                            sGp[(b * 4 + q) * 64] = make_float2(Gr[b][q], Gi[b][q]);
+                        }
+                        if (accept) {
+                            Xr[b][q] = xb_r;
+                            Xi[b][q] = xb_i;
+                        }
+                    } else {
+                        if (live) {
+                            Xpr[b][q] = Xr[b][q];
+                            Xpi[b][q] = Xi[b][q];
+                            Gpr[b][q] = Gr[b][q];
+                            Gpi[b][q] = Gi[b][q];
+                        }
+                        if (accept) {
+                            Xr[b][q] = XBr[b][q];
+                            Xi[b][q] = XBi[b][q];
+                        }
                     }
                 }
 #pragma unroll
