@@ -59,7 +59,9 @@ typedef enum {
  * accumulation.  Everything else (prox, step, reductions) is FP32; the
  * refinement and the final optimality check are FP64.  Shapes outside the MFMA
  * kernels (n > 64 or l > 512) run the wave-per-pixel kernel, whose contractions
- * are plain FP32 vector arithmetic under either setting. */
+ * are plain FP32 vector arithmetic: they, and the block form, take L1LS_FP32
+ * only and refuse L1LS_SPLIT_BF16 (L1LS_ERR_UNSUPPORTED_SHAPE, also from
+ * l1ls_workspace_size and l1ls_plan_create). */
 typedef enum { L1LS_FP32 = 0, L1LS_SPLIT_BF16 = 1 } l1ls_precision;
 
 /* Per-pixel status bits (diag.status). */
@@ -164,7 +166,7 @@ l1ls_status l1ls_solve_noalloc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *
  * 1/L_i), and the monotone test of Algorithm 1 on the objective with the block
  * replaced; the KKT residual is tested every J iterations.  J = 1 is Algorithm 1
  * with one block.  The FP64 refinement and certificate then run as in l1ls_solve
- * (opt->precision is ignored: the block products are FP32).
+ * (the block products are FP32: precision L1LS_SPLIT_BF16 is refused).
  *  blocks   J, 1 <= J <= min(64, l); n <= 64
  *  draws    device double, at least min(max_iter, polish_after) values in [0, 1),
  *           shared by all pixels (pixel-local iteration k uses draws[k-1])
@@ -247,6 +249,17 @@ l1ls_status l1ls_unrolled_backward(int32_t n, int32_t l, int64_t p, const float 
  * run.  `out` holds 5 entries. */
 l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *workspace,
                                 hipStream_t stream, uint64_t out[5]);
+
+/* Step constants of the last l1ls_solve or l1ls_solve_blocks with p > 0 that
+ * used `workspace` (synchronises `stream`): out[0] L_f = 2 lambda_max(A A^H),
+ * the Lipschitz constant of the gradient of ||Ax - b||^2 (Algorithm 1), found
+ * by an FP64 power iteration on the N x N matrix A A^H and used as the step
+ * floor 1/L_f of Eq. (15) and in the KKT residual; out[1] the initial step
+ * alpha_0 = 1/(2 max_l ||a_l||^2) that Eq. (15)'s backtracking starts from;
+ * out[2] the power iterations spent.  `out` holds 3 entries; a workspace that
+ * no such solve has used holds no meaningful values. */
+l1ls_status l1ls_solve_constants(int32_t n, int32_t l, int64_t p, const void *workspace,
+                                 hipStream_t stream, double out[3]);
 
 /* Name of a status code; detail of the last error on the calling thread. */
 const char *l1ls_status_string(l1ls_status s);

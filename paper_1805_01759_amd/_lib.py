@@ -28,6 +28,7 @@ EXPORTS = [
     "l1ls_unrolled_tape_size", "l1ls_unrolled_backward_ws_size", "l1ls_unrolled_forward",
     "l1ls_unrolled_backward", "l1ls_status_string", "l1ls_last_error",
     "l1ls_timing_enable", "l1ls_timing_read", "l1ls_timing_read_kernel", "l1ls_solve_counters",
+    "l1ls_solve_constants",
 ]
 
 # kernel classes for l1ls_timing_read_kernel
@@ -118,6 +119,8 @@ def load() -> ctypes.CDLL:
     L.l1ls_timing_read_kernel.restype = I32
     L.l1ls_solve_counters.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(ctypes.c_uint64 * 5)]
     L.l1ls_solve_counters.restype = st
+    L.l1ls_solve_constants.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(ctypes.c_double * 3)]
+    L.l1ls_solve_constants.restype = st
     _lib = L
     return L
 

@@ -160,6 +160,14 @@ def solve_counters(n: int, l: int, p: int, diag, stream=None):
     return tuple(int(v) for v in out)
 
 
+def solve_constants(n: int, l: int, p: int, diag, stream=None):
+    """(L_f, alpha_0, power iterations) of the solve that made `diag` (p > 0)."""
+    out = (ctypes.c_double * 3)()
+    _lib.check(_lib.load().l1ls_solve_constants(n, l, p, _ptr(diag["_ws"]), _stream(stream),
+                                                ctypes.byref(out)), "l1ls_solve_constants")
+    return tuple(float(v) for v in out)
+
+
 def timing_enable(on: bool = True) -> None:
     _lib.load().l1ls_timing_enable(int(on))
 

@@ -67,6 +67,16 @@ static l1ls_status check_shape(int32_t n, int32_t l, int64_t p)
     return L1LS_OK;
 }
 
+// Split-BF16 contractions exist in the MFMA kernels only; the shapes those do
+// not take (the wave-per-pixel kernel) refuse it rather than run FP32.
+static l1ls_status check_precision(int32_t n, int32_t l, const l1ls_options *o)
+{
+    if (o->precision == L1LS_SPLIT_BF16 && !mfma_supports(n, l))
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "split-BF16 needs n <= 64 and l <= 512 (got n = %d, l = %d)", n,
+                    l);
+    return L1LS_OK;
+}
+
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // Event timing of the solve's kernels (opt-in, for measurement), one list per
@@ -136,6 +146,8 @@ l1ls_status check_stack(int32_t n, int32_t l, int64_t p, const void *A, const vo
 // alternative tiling); warm starts need the split re/im or the wave kernel.
 l1ls_status stack_variant(int32_t n, int32_t l, const l1ls_options *opt, int choice, int alt, IterVariant *v)
 {
+    const l1ls_status st = check_precision(n, l, opt);
+    if (st != L1LS_OK) return st;
     if (choice == kMfma && !mfma_supports(n, l))
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
     if (!iter_variant(n, l, opt->precision, choice, alt, v))
@@ -344,6 +356,7 @@ l1ls_status l1ls_workspace_size(int32_t n, int32_t l, int64_t p, const l1ls_opti
     if (st != L1LS_OK) return st;
     if (opt) {
         st = check_options(opt);
+        if (st == L1LS_OK) st = check_precision(n, l, opt);
         if (st != L1LS_OK) return st;
     }
     *bytes = stack_workspace_layout(n, l, p).total;
@@ -392,6 +405,8 @@ l1ls_status l1ls_solve_blocks(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A
     if (blocks < 1 || blocks > kMaxBlocks || blocks > l)
         return fail(L1LS_ERR_INVALID_ARG, "blocks must be in [1, min(64, l)], got %d", blocks);
     if (n > 64) return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the block form takes n <= 64");
+    if (opt && opt->precision == L1LS_SPLIT_BF16)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the block form computes its products in FP32 only");
     if (!draws && p > 0) return fail(L1LS_ERR_INVALID_ARG, "draws is NULL");
     if (opt && fista_blocks_lds(n, lpad_for(l), blocks) > 64 * 1024)
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "block form needs more than 64 KB of LDS per pixel");
@@ -433,6 +448,23 @@ l1ls_status l1ls_solve_counters(int32_t n, int32_t l, int64_t p, const void *wor
     out[2] = q[1];
     out[3] = w2[2];
     out[4] = w2[3];
+    return L1LS_OK;
+}
+
+l1ls_status l1ls_solve_constants(int32_t n, int32_t l, int64_t p, const void *workspace, hipStream_t stream,
+                                 double out[3])
+{
+    if (!workspace || !out) return fail(L1LS_ERR_INVALID_ARG, "NULL pointer argument");
+    l1ls_status st = check_shape(n, l, p);
+    if (st != L1LS_OK) return st;
+    const StackWorkspace lay = stack_workspace_layout(n, l, p);
+    StackConsts c{};
+    hipError_t e = hipMemcpyAsync(&c, (const char *)workspace + lay.consts, sizeof c, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(L1LS_ERR_HIP, "constants read: %s", hipGetErrorString(e));
+    out[0] = c.lf;
+    out[1] = c.alpha0;
+    out[2] = c.lmax_it;
     return L1LS_OK;
 }
 

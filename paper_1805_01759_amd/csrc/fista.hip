@@ -22,7 +22,8 @@ __device__ __forceinline__ int rows_pad_for_dev(int n) { return 16 * ((n + 15) /
 //                                 its transpose l_pad x n
 //   setup_gram_kernel   (grid)    FP64 Gram M = A A^H, one entry per thread
 //   setup_power_kernel  (1 group) queue/counter reset, alpha0 = 1/(2 max_l ||a_l||^2),
-//                                 L_f = 2 lambda_max(M) by FP64 power iteration
+//                                 L_f = 2 lambda_max(M) by FP64 power iteration on
+//                                 M^(2^kSquarings), the Rayleigh quotient taken on M
 // Pointers of stack blockIdx.y's setup inputs and outputs.
 struct SetupView {
     int n, l, l_pad;
@@ -89,6 +90,13 @@ __global__ void __launch_bounds__(256) setup_gram_kernel(const StackTable t)
     }
 }
 
+// The power iteration runs on M^(2^kSquarings): where lambda_2 / lambda_1 = 1 - delta
+// its Rayleigh quotient on M converges as (1 - delta)^(2^(kSquarings+1)) per step, so
+// the 4,000-step cap leaves at most about 1 / (e 4000 2^(kSquarings+1)) relative
+// error in lambda_1 (about 5e-5 on M itself, 1e-8 here); the error is also never
+// above delta, which covers clustered top eigenvalues.
+constexpr int kSquarings = 12;
+
 __global__ void __launch_bounds__(256) setup_power_kernel(const StackTable t)
 {
     if (t.d[blockIdx.y].p <= 0) return;
@@ -122,22 +130,53 @@ __global__ void __launch_bounds__(256) setup_power_kernel(const StackTable t)
     }
     const double colmax = red[0][0];
     __syncthreads();
+    // P = M^(2^kSquarings) / scale: each square divided by the squared trace of its
+    // factor (M is PSD, so the trace of every scaled power lies in [1/N^2, 1])
+    const double2 *P = M;
+    for (int sq = 0; sq < kSquarings; ++sq) {
+        double2 *Q = const_cast<double2 *>(M) + (size_t)(1 + (sq & 1)) * n * n;
+        double tr = 0.0;
+        for (int i = tid; i < n; i += bd) tr += P[(size_t)i * n + i].x;
+        red[0][tid] = tr;
+        __syncthreads();
+        for (int s = bd / 2; s > 0; s >>= 1) {
+            if (tid < s) red[0][tid] += red[0][tid + s];
+            __syncthreads();
+        }
+        const double sc = red[0][0] > 0.0 ? 1.0 / (red[0][0] * red[0][0]) : 0.0;
+        __syncthreads();
+        for (int e = tid; e < n * n; e += bd) {
+            const int i = e / n, j = e % n;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const double2 x = P[(size_t)i * n + k], y = P[(size_t)k * n + j];
+                sr += x.x * y.x - x.y * y.y;
+                si += x.x * y.y + x.y * y.x;
+            }
+            Q[e] = make_double2(sr * sc, si * sc);
+        }
+        __threadfence();
+        __syncthreads();
+        P = Q;
+    }
     if (tid < n) v[tid] = make_double2(1.0 + 0.01 * tid, 0.001 * tid);
     __syncthreads();
     int it;
     double lam_prev = -1.0;
     for (it = 0; it < 4000; ++it) {
-        // w = M v ; Rayleigh quotient v^H M v / v^H v ; v = w / ||w||  (one fused reduction)
+        // w = P v ; Rayleigh quotient v^H M v / v^H v ; v = w / ||w||  (one fused reduction)
         double pr = 0.0, nv = 0.0, nw = 0.0;
         if (tid < n) {
-            double sr = 0.0, si = 0.0;
+            double sr = 0.0, si = 0.0, ur = 0.0, ui = 0.0;
             for (int kk = 0; kk < n; ++kk) {
-                const double2 m = M[tid * n + kk], x = v[kk];
-                sr += m.x * x.x - m.y * x.y;
-                si += m.x * x.y + m.y * x.x;
+                const double2 m = M[tid * n + kk], q = P[tid * n + kk], x = v[kk];
+                ur += m.x * x.x - m.y * x.y;
+                ui += m.x * x.y + m.y * x.x;
+                sr += q.x * x.x - q.y * x.y;
+                si += q.x * x.y + q.y * x.x;
             }
             wv[tid] = make_double2(sr, si);
-            pr = v[tid].x * sr + v[tid].y * si;  // Re(conj(v) w)
+            pr = v[tid].x * ur + v[tid].y * ui;  // Re(conj(v) M v)
             nv = v[tid].x * v[tid].x + v[tid].y * v[tid].y;
             nw = sr * sr + si * si;
         }
@@ -153,7 +192,7 @@ __global__ void __launch_bounds__(256) setup_power_kernel(const StackTable t)
             }
             __syncthreads();
         }
-        const double lam_est = red[0][0] / red[1][0];
+        const double lam_est = red[1][0] > 0.0 ? red[0][0] / red[1][0] : 0.0;  // A = 0: L_f = 0
         const double ww = red[2][0];
         const double inv = ww > 0.0 ? 1.0 / sqrt(ww) : 0.0;
         if (tid < n) v[tid] = make_double2(wv[tid].x * inv, wv[tid].y * inv);
@@ -279,7 +318,8 @@ size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precisi
     off += (size_t)waves * 16 * 16;
     off += 16;
     // 128 unknowns a wave: G_{k-1} of the tile's 16 pixels in LDS (float2 each)
-    if (l_pad / (16 * waves) >= 8) off += (size_t)16 * l_pad * sizeof(float2);
+    // and each wave's copy of r_{k-1} (16 T rows of the 16 pixels)
+    if (l_pad / (16 * waves) >= 8) off += (size_t)16 * l_pad * sizeof(float2) + (size_t)waves * T * 4 * 64 * sizeof(float2);
     return off;
 }
 
@@ -304,7 +344,7 @@ bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant 
     IterVariant r{};
     const int l_pad = lpad_for(l), waves = waves_for(l), T = rows_pad_for(n) / 16;
     if (choice == kWave || !mfma_supports(n, l)) {
-        if (alt != 0) return false;
+        if (alt != 0 || precision != L1LS_FP32) return false;
         r.family = kVarWave;
         r.nc = wave_chunks(l);
         r.waves = 1;

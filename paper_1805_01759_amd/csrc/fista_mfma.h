@@ -186,6 +186,8 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
     // of kept; the state then fits the registers of one wave per SIMD
     constexpr bool LEAN = KB >= 8;
     float2 *sGp = reinterpret_cast<float2 *>(smem + off) + (size_t)w * KB * 4 * 64 + lane;
+    // ... and each wave's copy of r_{k-1} (every wave holds the whole residual)
+    float2 *sRp = reinterpret_cast<float2 *>(smem + off) + (size_t)W * KB * 4 * 64 + (size_t)w * T * 4 * 64 + lane;
 
     fm::AView Av;
     if constexpr (BF) {
@@ -243,7 +245,11 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Rr[t][q] = Ri[t][q] = Rpr[t][q] = Rpi[t][q] = 0.0f;
+        for (int q = 0; q < 4; ++q) {
+            Rr[t][q] = Ri[t][q] = 0.0f;
+            if constexpr (LEAN) sRp[(t * 4 + q) * 64] = make_float2(0.0f, 0.0f);
+            else Rpr[t][q] = Rpi[t][q] = 0.0f;
+        }
 
     int64_t pix = -1;
     int k = 1;
@@ -314,8 +320,12 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
                 const float2 v = fresh && nn < n ? Bp[nn] : make_float2(0.0f, 0.0f);
                 Rr[t][q] = fresh ? -v.x : Rr[t][q];
                 Ri[t][q] = fresh ? -v.y : Ri[t][q];
-                Rpr[t][q] = fresh ? -v.x : Rpr[t][q];
-                Rpi[t][q] = fresh ? -v.y : Rpi[t][q];
+                if constexpr (LEAN) {
+                    if (fresh) sRp[(t * 4 + q) * 64] = make_float2(-v.x, -v.y);
+                } else {
+                    Rpr[t][q] = fresh ? -v.x : Rpr[t][q];
+                    Rpi[t][q] = fresh ? -v.y : Rpi[t][q];
+                }
                 bb = fmaf(v.x, v.x, fmaf(v.y, v.y, bb));
             }
         bb = fm::sum_h(bb);
@@ -401,8 +411,12 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
                     const float r_r = wr[q] + Rr[t][q], r_i = wi[q] + Ri[t][q];  // A x0 - b
                     Rr[t][q] = fresh ? r_r : Rr[t][q];
                     Ri[t][q] = fresh ? r_i : Ri[t][q];
-                    Rpr[t][q] = fresh ? r_r : Rpr[t][q];
-                    Rpi[t][q] = fresh ? r_i : Rpi[t][q];
+                    if constexpr (LEAN) {
+                        if (fresh) sRp[(t * 4 + q) * 64] = make_float2(r_r, r_i);
+                    } else {
+                        Rpr[t][q] = fresh ? r_r : Rpr[t][q];
+                        Rpi[t][q] = fresh ? r_i : Rpi[t][q];
+                    }
                     rr = fmaf(r_r, r_r, fmaf(r_i, r_i, rr));
                 }
             }
@@ -458,14 +472,16 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
             return;
         }
         float r2r[T][4], r2i[T][4], nr2r[T][4];
+        if constexpr (!LEAN) {
 #pragma unroll
-        for (int t = 0; t < T; ++t)
+            for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                r2r[t][q] = 2.0f * Rr[t][q];
-                r2i[t][q] = 2.0f * Ri[t][q];
-                nr2r[t][q] = -2.0f * Rr[t][q];
-            }
+                for (int q = 0; q < 4; ++q) {
+                    r2r[t][q] = 2.0f * Rr[t][q];
+                    r2i[t][q] = 2.0f * Ri[t][q];
+                    nr2r[t][q] = -2.0f * Rr[t][q];
+                }
+        }
 #pragma unroll
         for (int b = 0; b < KB; ++b) {
             f4 gr = f4{0.0f, 0.0f, 0.0f, 0.0f}, gi = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -475,10 +491,14 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const float2 av = Av.load2(16 * t + 4 * h + q, m);
-                    gr = fm::mfma(av.x, r2r[t][q], gr);
-                    gr = fm::mfma(av.y, r2i[t][q], gr);
-                    gi = fm::mfma(av.x, r2i[t][q], gi);
-                    gi = fm::mfma(av.y, nr2r[t][q], gi);
+                    // LEAN forms 2 r on the fly (three registers fewer per residual entry)
+                    const float pr = LEAN ? 2.0f * Rr[t][q] : r2r[t][q];
+                    const float pi = LEAN ? 2.0f * Ri[t][q] : r2i[t][q];
+                    const float npr = LEAN ? -2.0f * Rr[t][q] : nr2r[t][q];
+                    gr = fm::mfma(av.x, pr, gr);
+                    gr = fm::mfma(av.y, pi, gr);
+                    gi = fm::mfma(av.x, pi, gi);
+                    gi = fm::mfma(av.y, npr, gi);
                 }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -772,8 +792,17 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
             for (int t = 0; t < T; ++t)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float dr_r = fmaf(beta, Rr[t][q] - Rpr[t][q], Wr[t][q]);
-                    const float dr_i = fmaf(beta, Ri[t][q] - Rpi[t][q], Wi[t][q]);
+                    float rp_r, rp_i;
+                    if constexpr (LEAN) {
+                        const float2 r2 = sRp[(t * 4 + q) * 64];
+                        rp_r = r2.x;
+                        rp_i = r2.y;
+                    } else {
+                        rp_r = Rpr[t][q];
+                        rp_i = Rpi[t][q];
+                    }
+                    const float dr_r = fmaf(beta, Rr[t][q] - rp_r, Wr[t][q]);
+                    const float dr_i = fmaf(beta, Ri[t][q] - rp_i, Wi[t][q]);
                     Rbr[t][q] = Rr[t][q] + dr_r;
                     Rbi[t][q] = Ri[t][q] + dr_i;
                     dfr = fmaf(dr_r, Rbr[t][q] + Rr[t][q], fmaf(dr_i, Rbi[t][q] + Ri[t][q], dfr));
@@ -820,8 +849,12 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (live) {
-                        Rpr[t][q] = Rr[t][q];
-                        Rpi[t][q] = Ri[t][q];
+                        if constexpr (LEAN) {
+                            sRp[(t * 4 + q) * 64] = make_float2(Rr[t][q], Ri[t][q]);
+                        } else {
+                            Rpr[t][q] = Rr[t][q];
+                            Rpi[t][q] = Ri[t][q];
+                        }
                     }
                     if (accept) {
                         Rr[t][q] = Rbr[t][q];

@@ -143,8 +143,8 @@ __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, i
     off = ws_align(off + (size_t)rows_pad_for(n) * l_pad * sizeof(float2));
     w.a_trans = off;
     off = ws_align(off + (size_t)l_pad * n * sizeof(float2));
-    w.gram = off;
-    off = ws_align(off + (size_t)n * n * sizeof(double2));
+    w.gram = off;  // M = A A^H, then two N x N buffers for its repeated squares
+    off = ws_align(off + (size_t)3 * n * n * sizeof(double2));
     w.consts = off;
     off = ws_align(off + sizeof(StackConsts));
     w.queue = off;

@@ -162,7 +162,7 @@ IterVariant autotune(int n, int l, const l1ls_options &opt, int dev)
         if (mfma_supports(n, l) && iter_variant(n, l, opt.precision, kMfma, alt, &probe) &&
             !(opt.warm_start && probe.family == kVarEmbedded))
             cands.push_back({kMfma, alt});
-    cands.push_back({kWave, 0});
+    if (opt.precision == L1LS_FP32) cands.push_back({kWave, 0});  // the wave kernel is FP32 only
     IterVariant best_v;
     iter_variant(n, l, opt.precision, cands[0].first, cands[0].second, &best_v);
     if (cands.size() > 1) {

@@ -701,7 +701,10 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
                 acc += lam * sqrt((double)v.x * v.x + (double)v.y * v.y);
             }
             fbest = wsum(acc) * (1.0 + 1e-3);
-        } else if (a.mode == 1 && (a.status[p] & L1LS_PX_MAX_ITER) != 0) {
+        } else if (a.mode == 2 || (a.status[p] & L1LS_PX_MAX_ITER) != 0) {
+            // only the objective of the starting point is needed (mode 2 refines
+            // every pixel; a capped pixel without a kept residual): FP64 from the
+            // residual of its nonzero bins
             residual_start(a, sh, b, xo);
             fl += f8n * (unsigned long long)sh.cnt;
             double acc = 0.0;
@@ -712,7 +715,8 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
             }
             fbest = wsum(acc);
         } else {
-            // objective and FP64 natural KKT residual of the starting point
+            // mode 1, a pixel the FP32 stage retired: objective and FP64 natural
+            // KKT residual of the starting point decide whether it is solved
             residual_start(a, sh, b, xo);
             fl += f8n * (unsigned long long)sh.cnt;
             double kk0;
@@ -721,7 +725,7 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
             full_pass<true, false>(a, sh, xo, 0, sh.cnt, lam, lf, inv_lf, fbest, kk0, vdummy);
             fl += f8n * (unsigned long long)a.l;
             __syncthreads();
-            if (a.mode == 1 && kk0 <= (double)a.tol) continue;  // already solved
+            if (kk0 <= (double)a.tol) continue;  // already solved
         }
         have_c = false;
         // -- working set: the local maxima of |x| (FISTA spreads one scatterer

@@ -109,3 +109,22 @@ def test_warm_start_refused_where_unsupported(L):
                              ctypes.byref(o), 2, ctypes.c_void_p(512), ctypes.c_void_p(128), None,
                              ctypes.c_void_p(256), 1 << 20, None)
     assert st == -2 and b"block form" in L.l1ls_last_error()
+
+
+def test_split_bf16_refused_without_an_mfma_kernel(L):
+    # split-BF16 exists in the MFMA kernels (n <= 64, l <= 512) only: the wave-per-pixel
+    # shapes and the block form refuse it instead of computing in FP32
+    o = L.l1ls_options_default()
+    o.precision = 1
+    assert _ws(L, 64, 512, 1, o)[0] == 0
+    for n, l in ((65, 256), (50, 513), (128, 1024)):
+        assert _ws(L, n, l, 1, o)[0] == -2
+        assert b"split-BF16" in L.l1ls_last_error()
+        assert _solve(L, n=n, l=l, o=o, wsb=1 << 26) == -2
+    o.precision = 0
+    assert _ws(L, 128, 1024, 1, o)[0] == 0
+    o.precision = 1
+    st = L.l1ls_solve_blocks(4, 8, 3, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(64), 0,
+                             ctypes.byref(o), 2, ctypes.c_void_p(512), ctypes.c_void_p(128), None,
+                             ctypes.c_void_p(256), 1 << 20, None)
+    assert st == -2 and b"FP32 only" in L.l1ls_last_error()

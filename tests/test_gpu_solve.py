@@ -189,6 +189,48 @@ def test_determinism_and_batch_independence(dev):
     assert torch.equal(Xs, X1[1000:1517])
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("polish", [1, 2])
+def test_determinism_with_fp64_stage(dev, precision, polish):
+    """The default path (FP32 stage, then the FP64 refinement whose workgroups take
+    pixels from a shared counter, then the certificate) is bitwise repeatable and
+    independent of the batch a pixel is solved in."""
+    A, B, lam = _case(2, 0, 4096)
+    Ad, Bd, ld = _to_dev(dev, A, B, lam)
+    kw = dict(fp64_polish=polish, polish_after=12, precision=precision)
+    X1, d1 = api.solve(Ad, Bd, ld, **kw)
+    X2, d2 = api.solve(Ad, Bd, ld, **kw)
+    assert torch.equal(X1, X2)
+    for k in ("kkt", "objective", "iters", "status", "nnz"):
+        assert torch.equal(d1[k], d2[k]), k
+    Xs, ds = api.solve(Ad, Bd[1000:1517].contiguous(), ld[1000:1517].contiguous(), **kw)
+    assert torch.equal(Xs, X1[1000:1517])
+    assert torch.equal(ds["kkt"], d1["kkt"][1000:1517])
+
+
+@pytest.mark.parametrize("gap", [0.5, 1.25e-4, 1e-6, 0.0])
+def test_lipschitz_constant_clustered_spectra(dev, gap):
+    """The device L_f = 2 lambda_max(A A^H) against eigvalsh when the top two
+    eigenvalues are 1 and 1 - gap (before A is rounded to FP32).  A plain power
+    iteration capped at 4,000 steps errs most near gap = 1.25e-4 (about 5e-5
+    relative); alpha_0 = 1/(2 max_l ||a_l||^2) is checked beside it."""
+    rng = np.random.default_rng(7)
+    n, l, p = 24, 200, 8
+    U = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))[0]
+    V = np.linalg.qr(rng.standard_normal((l, n)) + 1j * rng.standard_normal((l, n)))[0]
+    sig2 = 37.0 * np.concatenate([[1.0, 1.0 - gap], np.linspace(0.9, 0.1, n - 2)])
+    A = ((U * np.sqrt(sig2)) @ V.conj().T).astype(np.complex64)
+    A64 = A.astype(np.complex128)
+    want = 2 * np.linalg.eigvalsh(A64 @ A64.conj().T).max()
+    B = (A64 @ (rng.standard_normal((l, p)) * (rng.random((l, p)) < 0.02))).T.astype(np.complex64)
+    lam = np.full(p, 0.5, np.float32)
+    Ad, Bd, ld = _to_dev(dev, A, B, lam)
+    _, d = api.solve(Ad, Bd, ld, max_iter=2, fp64_polish=0)
+    lf, a0, its = api.solve_constants(n, l, p, d)
+    assert abs(lf / want - 1) <= 2e-8, (lf, want, its)
+    assert a0 == pytest.approx(1 / (2 * (np.abs(A64) ** 2).sum(axis=0).max()), rel=1e-12)
+
+
 def test_scene_scale_sampled(dev, orc):
     """Full 2^20-pixel stack in the benchmark's launch configuration; 256 sampled pixels."""
     A, B, lam = _case(2)
