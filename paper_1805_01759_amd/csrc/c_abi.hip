@@ -225,8 +225,10 @@ l1ls_status run_stacks(const StackDesc *d, const IterVariant *var, int count, co
     if (opt->fp64_polish) {
         TimedLaunch tl(s, L1LS_KERNEL_REFINE);
         e = chunks([&](const StackTable &t) { return launch_polish_table(t, s); });
-        // pixels whose 16-slot working set filled above tol: the 32-slot pass starts
-        // from the point the first one left in X (its FP64 objective is recomputed)
+        // pixels whose 8-slot (then 16-slot) working set filled above tol: the next
+        // pass starts from the point the last one left in X (its FP64 objective is
+        // recomputed)
+        if (e == hipSuccess) e = chunks([&](const StackTable &t) { return launch_polish_mid_table(t, s); });
         if (e == hipSuccess) e = chunks([&](const StackTable &t) { return launch_polish_wide_table(t, s); });
         if (e != hipSuccess) return fail(L1LS_ERR_HIP, "refinement launch: %s", hipGetErrorString(e));
     }
@@ -285,6 +287,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     if (opt->fp64_polish) {
         TimedLaunch tl(s, L1LS_KERNEL_REFINE);
         e = launch_polish_table(t, s);
+        if (e == hipSuccess) e = launch_polish_mid_table(t, s);
         if (e == hipSuccess) e = launch_polish_wide_table(t, s);
         if (e != hipSuccess) return fail(L1LS_ERR_HIP, "refinement launch: %s", hipGetErrorString(e));
     }

@@ -246,11 +246,16 @@ __host__ __device__ inline FistaArgs fista_args_for(const StackDesc &d, const So
     return fa;
 }
 
-// wide: the 32-slot pass over the pixels the 16-slot pass listed
-__host__ __device__ inline PolishArgsDev polish_args_for(const StackDesc &d, const SolveOpts &o, bool wide)
+// The refinement runs in three passes of growing working sets (tier 0: 8 slots,
+// 1: 16, 2: 32); each takes the pixels the previous one listed because its working
+// set filled above tol.  The lists alternate between two regions: tier 0 reads
+// the refinement list and writes the overflow region, tier 1 reads that and
+// writes the (by then finished) refinement list, tier 2 reads it.
+__host__ __device__ inline PolishArgsDev polish_args_for(const StackDesc &d, const SolveOpts &o, int tier)
 {
     const StackWorkspace lay = stack_workspace_layout(d.n, d.l, d.p);
     uint32_t *queue = (uint32_t *)(d.ws + lay.queue);
+    int32_t *plist = (int32_t *)(d.ws + lay.polish_list), *oflow = (int32_t *)(d.ws + lay.overflow);
     PolishArgsDev pa;
     pa.n = d.n;
     pa.l = d.l;
@@ -261,12 +266,12 @@ __host__ __device__ inline PolishArgsDev polish_args_for(const StackDesc &d, con
     pa.lambda_stride = d.lambda_stride;
     pa.X = d.X;
     pa.consts = (const StackConsts *)(d.ws + lay.consts);
-    pa.count = wide ? queue + 3 : queue + 1;
-    pa.next = wide ? queue + 4 : queue + 2;
-    pa.list = wide ? (const int32_t *)(d.ws + lay.overflow) : (const int32_t *)(d.ws + lay.polish_list);
-    pa.R = (!wide && d.keep_residual) ? (const float2 *)(d.ws + lay.resid) : nullptr;
-    pa.overflow = wide ? nullptr : (int32_t *)(d.ws + lay.overflow);
-    pa.overflow_count = wide ? nullptr : queue + 3;
+    pa.count = queue + 1 + 2 * tier;  // counts in queue[1], [3], [5]; next pixel in [2], [4], [6]
+    pa.next = queue + 2 + 2 * tier;
+    pa.list = tier == 1 ? oflow : plist;
+    pa.R = (tier == 0 && d.keep_residual) ? (const float2 *)(d.ws + lay.resid) : nullptr;
+    pa.overflow = tier == 0 ? oflow : (tier == 1 ? plist : nullptr);
+    pa.overflow_count = tier < 2 ? queue + 3 + 2 * tier : nullptr;
     pa.status = (uint32_t *)(d.ws + lay.status);
     pa.work = (unsigned long long *)(d.ws + lay.work);
     pa.H = (const double2 *)(d.ws + lay.hgram);
@@ -307,7 +312,8 @@ __host__ __device__ inline CertifyArgs certify_args_for(const StackDesc &d, cons
 // Launches over a stack table (every entry with p > 0).
 hipError_t launch_setup_table(const StackTable &t, bool bin_gram, hipStream_t s);
 hipError_t launch_certify_table(const StackTable &t, hipStream_t s);
-hipError_t launch_polish_table(const StackTable &t, hipStream_t s);       // 16 slots
+hipError_t launch_polish_table(const StackTable &t, hipStream_t s);       // 8 slots
+hipError_t launch_polish_mid_table(const StackTable &t, hipStream_t s);   // 16 slots
 hipError_t launch_polish_wide_table(const StackTable &t, hipStream_t s);  // 32 slots
 
 // The iteration kernel that runs a stack: the split re/im MFMA tile (T row

@@ -52,21 +52,35 @@ __device__ __forceinline__ float lane_value_f(float v, int i)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
 }
 
-// Newton on at most kMaxSupp complex unknowns: 16 for the first pass; a second
-// build with 32 takes the pixels whose working set filled up before the target
+// Newton on at most kMaxSupp complex unknowns: 8 for the first pass (small
+// working sets keep a workgroup's LDS near 10 KB at N = 50, L = 512, so three
+// waves share a SIMD); builds with 16 and then 32 take the pixels whose working
+// set filled up before the target
 #ifndef L1LS_POLISH_SUPP
-#define L1LS_POLISH_SUPP 16
+#define L1LS_POLISH_SUPP 8
 #endif
 constexpr int kMaxSupp = L1LS_POLISH_SUPP;
-static_assert(kMaxSupp == 16 || kMaxSupp == 32, "working sets of 16 or 32 slots");
-// violators admitted per round: the wide pass grows its set by up to 8 a round
-// (the next-largest violations of distinct lanes), the first pass by one
+static_assert(kMaxSupp == 8 || kMaxSupp == 16 || kMaxSupp == 32, "working sets of 8, 16 or 32 slots");
+// violators admitted per round: the 32-slot pass grows its set by up to 8 a round
+// (the next-largest violations of distinct lanes), the 8- and 16-slot passes by one
 constexpr int kEnter = kMaxSupp == 32 ? 8 : 1;
+constexpr int kTier = kMaxSupp == 8 ? 0 : (kMaxSupp == 16 ? 1 : 2);
 constexpr int kMaxM = 2 * kMaxSupp;   // real Hessian order
 constexpr int kTri = kMaxM * (kMaxM + 1) / 2;
 constexpr int kGc = kMaxSupp * (kMaxSupp + 1) / 2;
+// the register solver's transpose (order <= 16) sits past the packed Hessian
+constexpr int kHLen = kTri >= 136 + 256 ? kTri : 136 + 256;
 
 __device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }  // k <= i
+
+// Dynamic LDS of one workgroup: r and w (n double2 each; the FP32 copy of r that
+// a pass reads lives in w's space), A_S (n x kMaxSupp float2, whose space first
+// holds the nonzero-bin list of the starting point), the slot index of each bin.
+static __host__ __device__ inline size_t polish_as_bytes(int n, int l_pad)  // per build (16 or 32 slots)
+{
+    const size_t as = (size_t)n * kMaxSupp * sizeof(float2), nz = (size_t)l_pad * sizeof(int16_t);
+    return ((as > nz ? as : nz) + 15) / 16 * 16;
+}
 
 struct PolishShared {
     double2 *r;         // n: residual A x - b (dynamic LDS)
@@ -75,7 +89,7 @@ struct PolishShared {
     float2 *AS;         // n x kMaxSupp: columns of the working set (dynamic LDS)
     int16_t *nzl;       // l_pad: nonzero bins of the starting point (dynamic LDS)
     int8_t *sidx;       // l_pad: slot of bin m in the working set, or -1 (dynamic LDS)
-    double H[kTri];     // packed lower triangle of the real Hessian / its Cholesky factor
+    double H[kHLen];    // packed lower triangle of the real Hessian / its Cholesky factor
     double2 Gc[kGc];    // packed lower triangle of the Gram G = A_S^H A_S (Hermitian)
     double2 z[kMaxSupp], c[kMaxSupp];  // working-set point and A_S^H r
     double ur[kMaxSupp], ui[kMaxSupp], iz[kMaxSupp];  // z/|z| and 1/|z| per slot
@@ -617,7 +631,7 @@ __device__ bool newton_regs(PolishShared &sh, int m2, double mu, double &d)
     // U^T d = w: U_ji (i < j) is lane j's row[i]; the factor is transposed through
     // LDS (past the packed Hessian, which a retry with a shift still needs) so
     // that lane i holds column i of U
-    double *T = sh.H + kTri - NS * NS;
+    double *T = sh.H + kHLen - NS * NS;
     if (lane < NS) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) T[lane * NS + k] = row[k];
@@ -642,13 +656,11 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
         sh.r = reinterpret_cast<double2 *>(p);
         p += (size_t)a.n * sizeof(double2);
         sh.w = reinterpret_cast<double2 *>(p);
+        sh.r32 = reinterpret_cast<float2 *>(p);  // the pass's copy of r shares w's space
         p += (size_t)a.n * sizeof(double2);
-        sh.r32 = reinterpret_cast<float2 *>(p);
-        p += (size_t)a.n * sizeof(float2);
         sh.AS = reinterpret_cast<float2 *>(p);
-        p += (size_t)a.n * kMaxSupp * sizeof(float2);
-        sh.nzl = reinterpret_cast<int16_t *>(p);
-        p += (size_t)a.l_pad * sizeof(int16_t);
+        sh.nzl = reinterpret_cast<int16_t *>(p);  // used before A_S is staged
+        p += polish_as_bytes(a.n, a.l_pad);
         sh.sidx = reinterpret_cast<int8_t *>(p);
     }
     __syncthreads();
@@ -825,6 +837,11 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
         // z += t d by r += t A_S d, c += t G d and the change the line search
         // measured, a drop or an entry by the column's rank-one term.
         bool fresh = true;
+        // Newton on a working set stops at gstop, except in mode 2 while the full
+        // pass still finds violators: there the set is about to change and a
+        // subproblem solved to mode 1's accuracy picks the same violator, so the
+        // tight target is taken only once the set looks final
+        double gcur = a.mode == 2 ? 1e-2 * (double)a.tol : gstop;
         double ph = 0.0;
         for (int round = 0; round < a.rounds; ++round) {
             for (int it = 0; it < 50 && s > 0; ++it) {
@@ -843,7 +860,11 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
                             gi += av.x * rv.y - av.y * rv.x;
                         }
                     }
-                    if (NG == 4) {
+                    if (NG >= 8) {
+                        gr += __shfl_xor(gr, 8, 64);
+                        gi += __shfl_xor(gi, 8, 64);
+                    }
+                    if (NG >= 4) {
                         gr += __shfl_xor(gr, 16, 64);
                         gi += __shfl_xor(gi, 16, 64);
                     }
@@ -870,7 +891,7 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
                 }
                 gmax = wmax(gmax);
                 __syncthreads();
-                if (gmax <= gstop * lam) break;
+                if (gmax <= gcur * lam) break;
                 // Newton direction; shifted retries while the Hessian is not PD
                 double mu = 0.0, dv = 0.0;
                 bool ok = false;
@@ -1054,7 +1075,13 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
             for (int t = lane; t < s; t += 64) sh.sidx[sh.S[t]] = -1;
             __syncthreads();
             if (kk <= kstop) break;
-            if (vidx < 0) break;
+            if (vidx < 0) {
+                if (gcur > gstop) {  // no violator left: the same set to the tight target
+                    gcur = gstop;
+                    continue;
+                }
+                break;
+            }
             if (s >= kMaxSupp) {
                 // the working set is full and the point is not solved: a wider pass
                 // (a later launch) takes the pixel from its best point so far
@@ -1117,7 +1144,13 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
                 fl += f8n + 8ull * (unsigned long long)s;
             }
             }
-            if (entered == 0) break;
+            if (entered == 0) {
+                if (gcur > gstop) {
+                    gcur = gstop;
+                    continue;
+                }
+                break;
+            }
         }
         // write the best point (complex64) unless it is the starting one
         if (sh.sb >= 0) {
@@ -1145,7 +1178,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
 {
     for (int i = 0; i < t.count; ++i) {
         if (t.d[i].p <= 0) continue;
-        const PolishArgsDev a = polish_args_for(t.d[i], t.o, kMaxSupp == 32);
+        const PolishArgsDev a = polish_args_for(t.d[i], t.o, kTier);
         if ((int)blockIdx.x >= a.max_groups) continue;
         polish_stack(a);
         __syncthreads();
@@ -1154,9 +1187,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) po
 
 size_t polish_lds_bytes(int n, int l_pad)
 {
-    return (size_t)2 * n * sizeof(double2) + (size_t)n * sizeof(float2) +
-           (size_t)l_pad * (sizeof(int16_t) + sizeof(int8_t)) +
-           (size_t)n * kMaxSupp * sizeof(float2);
+    return (size_t)2 * n * sizeof(double2) + polish_as_bytes(n, l_pad) + (size_t)l_pad * sizeof(int8_t);
 }
 
 hipError_t launch_polish_table(const StackTable &t, hipStream_t s)
