@@ -145,7 +145,7 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
  * is created.  The stream must belong to the current device.
  *  - returns L1LS_ERR_WORKSPACE, with no work queued, when l1ls_workspace_size
  *    for (n, l, p) exceeds L1LS_NOALLOC_SCRATCH_BYTES (e.g. n = 25, l = 256
- *    holds about 240,000 pixels, n = 50, l = 512 about 88,000); split the
+ *    holds about 220,000 pixels, n = 50, l = 512 about 68,000); split the
  *    pixels or call l1ls_solve.
  *  - every call on one device shares that device's array, which keeps the last
  *    call's contents (the kernels clear what must start at zero): calls that

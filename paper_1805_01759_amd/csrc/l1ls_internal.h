@@ -112,9 +112,10 @@ struct PolishArgsDev {
     int32_t max_groups;       // workgroups the launch may use (<= kMaxRefineGroups)
 };
 
-// The refinement launches at most this many workgroups (12 per CU on 256 CUs):
-// each holds A^H b of its current pixel in the workspace.
-constexpr int kMaxRefineGroups = 3072;
+// The refinement launches at most this many workgroups (16 per CU on 256 CUs,
+// four single-wave workgroups a SIMD): each holds A^H b of its current pixel in
+// the workspace.
+constexpr int kMaxRefineGroups = 4096;
 
 // Tiling helpers (host and device): KB MFMA row blocks of 16 unknowns per wave
 // slice, W waves, l padded to 8 KB W, 2N real rows in 16-row blocks, N padded to 16.

@@ -1174,7 +1174,11 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
 // The stacks of a table one after another: each workgroup takes listed pixels
 // of a stack from that stack's counter, then moves on.  A workgroup beyond a
 // stack's number of A^H b buffers skips that stack (the others cover it).
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) polish_kernel(const StackTable t)
+// The 8-slot pass is built for four waves a SIMD (128 VGPRs, some of the register
+// solver's rows spill): it is latency bound, and the extra wave per SIMD more than
+// pays for the spills (close pairs: 704 -> 642 ms); the larger passes keep three.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMaxSupp == 8 ? 4 : 3)))
+polish_kernel(const StackTable t)
 {
     for (int i = 0; i < t.count; ++i) {
         if (t.d[i].p <= 0) continue;
