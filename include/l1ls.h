@@ -83,16 +83,16 @@ typedef struct {
     int32_t monotone;      /* 1: accept x-bar only if F(x-bar) <= F(x^k) (Algorithm 1)         */
     int32_t fp64_polish;   /* FP64 active-set Newton refinement: 0 off; 1 pixels whose FP64
                               KKT residual exceeds tol; 2 every pixel (to FP64 precision).
-                              Working sets of up to 16 complex unknowns, then a second pass
-                              with up to 32 for pixels that filled the first; a pixel whose
-                              minimiser has more nonzeros is returned unsolved (status bits) */
+                              Working sets of up to 8 complex unknowns, then passes with up
+                              to 16 and 32 for pixels that filled the previous one; a pixel
+                              whose minimiser has more nonzeros is returned unsolved (status
+                              bits)                                                          */
     int32_t polish_after;  /* hand a pixel to the refinement after this many iterations
                               (<= max_iter; <= 0 means max_iter)                              */
     int32_t warm_start;    /* 0: Algorithm 1 starts at x^(0) = 0; 1: X holds each pixel's
                               initial point x^(0) on entry (the Init of Algorithm 1; x^(1) =
                               x^(0), the step starts at alpha_0).  Not available in
-                              l1ls_solve_blocks or with split-BF16 for l > 256
-                              (L1LS_ERR_UNSUPPORTED_SHAPE)                                   */
+                              l1ls_solve_blocks (L1LS_ERR_UNSUPPORTED_SHAPE)                 */
 } l1ls_options;
 
 /* Device arrays of length P; any may be NULL.

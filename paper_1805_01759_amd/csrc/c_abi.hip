@@ -143,7 +143,7 @@ l1ls_status check_stack(int32_t n, int32_t l, int64_t p, const void *A, const vo
 }
 
 // The iteration variant of a stack (choice kAuto / kMfma / kWave, `alt` an
-// alternative tiling); warm starts need the split re/im or the wave kernel.
+// alternative tiling).
 l1ls_status stack_variant(int32_t n, int32_t l, const l1ls_options *opt, int choice, int alt, IterVariant *v)
 {
     const l1ls_status st = check_precision(n, l, opt);
@@ -152,9 +152,6 @@ l1ls_status stack_variant(int32_t n, int32_t l, const l1ls_options *opt, int cho
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "MFMA kernel needs n <= 64, l <= 512");
     if (!iter_variant(n, l, opt->precision, choice, alt, v))
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "no iteration kernel variant %d for n = %d, l = %d", alt, n, l);
-    if (opt->warm_start && v->family == kVarEmbedded)
-        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "warm_start with split-BF16 needs l <= 256 (n = %d, l = %d)",
-                    n, l);
     return L1LS_OK;
 }
 

@@ -29,6 +29,7 @@ struct SetupView {
     int n, l, l_pad;
     const float2 *A;
     float2 *Ap, *At;
+    uint16_t *Abf;
     double2 *gram, *H;
     StackConsts *consts;
     uint32_t *queue;
@@ -44,6 +45,7 @@ __device__ inline SetupView setup_view(const StackDesc &d)
     v.A = d.A;
     v.Ap = (float2 *)(d.ws + lay.a_packed);
     v.At = (float2 *)(d.ws + lay.a_trans);
+    v.Abf = (uint16_t *)(d.ws + lay.a_bf16);
     v.gram = (double2 *)(d.ws + lay.gram);
     v.H = (double2 *)(d.ws + lay.hgram);
     v.consts = (StackConsts *)(d.ws + lay.consts);
@@ -68,6 +70,23 @@ __global__ void __launch_bounds__(256) setup_pack_kernel(const StackTable t)
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)l_pad * n; idx += stride) {
         const int c = (int)(idx / n), r = (int)(idx % n);  // transposed copy (column reads coalesce)
         At[idx] = c < l ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
+    }
+    // split-BF16 planes for the MFMA kernel that reads them from L2: x = hi + lo,
+    // hi = RNE bf16(x), lo = RNE bf16(x - hi); planes re hi, im hi, re lo, im lo,
+    // row-major (forward product) and transposed (adjoint)
+    uint16_t *Fp = sv.Abf, *Tp = sv.Abf + (size_t)4 * rows * l_pad;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)rows * l_pad; idx += stride) {
+        const int r = (int)(idx / l_pad), c = (int)(idx % l_pad);
+        const float2 v = (r < n && c < l) ? A[(size_t)r * l + c] : make_float2(0.0f, 0.0f);
+        const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+        const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
+        const uint16_t pv[4] = {__builtin_bit_cast(uint16_t, rh), __builtin_bit_cast(uint16_t, ih),
+                                __builtin_bit_cast(uint16_t, rl), __builtin_bit_cast(uint16_t, il)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            Fp[((size_t)q * rows + r) * l_pad + c] = pv[q];
+            Tp[((size_t)q * l_pad + c) * rows + r] = pv[q];
+        }
     }
 }
 
@@ -310,9 +329,9 @@ size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precisi
 {
     const int rows = rows_pad_for(n), T = rows / 16;
     size_t off = 0;
-    if (precision == L1LS_SPLIT_BF16)
+    if (precision == L1LS_SPLIT_BF16 && a_lds)
         off = (fm_bf_planes_bytes_host(rows, l_pad) + 15) & ~(size_t)15;
-    else if (a_lds)
+    else if (a_lds && precision == L1LS_FP32)
         off = ((size_t)rows * (l_pad + 2) * sizeof(float2) + 15) & ~(size_t)15;
     off += (size_t)waves * 2 * T * 64 * 16;
     off += (size_t)waves * 16 * 16;
@@ -358,14 +377,12 @@ bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant 
     probe.l_pad = l_pad;
     probe.waves = waves;
     if (precision == L1LS_SPLIT_BF16) {
+        // the planes of A in LDS where they fit (up to 32 rows at L <= 256), else
+        // read from their workspace copy (L2); 64 (L <= 256) or 128 unknowns a wave
         if (alt != 0) return false;
-        if (slice_blocks_for(l) == 8 && mfma_lds_fits(probe, L1LS_SPLIT_BF16) && T <= 4) {
-            r = IterVariant{kVarMfma, T, 4, 1, L1LS_SPLIT_BF16, 4, waves, 0};
-        } else {
-            const int zb = zblocks_for(n);
-            r = IterVariant{kVarEmbedded, zb, slice_blocks_for(l), fista_a_fits_lds(n, l_pad, waves, zb) ? 1 : 0,
-                            L1LS_SPLIT_BF16, 4, waves, 0};
-        }
+        const int KB = slice_blocks_for(l) == 8 ? 4 : 8;
+        const bool lds = KB == 4 && mfma_lds_fits(probe, L1LS_SPLIT_BF16);
+        r = IterVariant{kVarMfma, T, KB, lds ? 1 : 0, L1LS_SPLIT_BF16, 4, waves, 0};
         *v = r;
         return true;
     }
@@ -401,7 +418,11 @@ template <int T, int PREC>
 static hipError_t launch_mfma_t(const StackTable &t, const IterVariant &v, hipStream_t s)
 {
     if constexpr (PREC == L1LS_SPLIT_BF16) {
-        return launch_mfma_one<T, 4, true, L1LS_SPLIT_BF16, 4>(t, v.waves, s);
+        if (v.KB == 4)
+            return v.alds ? launch_mfma_one<T, 4, true, L1LS_SPLIT_BF16, 4>(t, v.waves, s)
+                          : launch_mfma_one<T, 4, false, L1LS_SPLIT_BF16, 4>(t, v.waves, s);
+        if (v.KB == 8) return launch_mfma_one<T, 8, false, L1LS_SPLIT_BF16, 4>(t, v.waves, s);
+        return hipErrorInvalidValue;
     } else {
         if constexpr (T <= 2) {
             if (v.KB == 2)

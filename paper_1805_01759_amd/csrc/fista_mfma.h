@@ -40,10 +40,12 @@
 // hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b) with x = hi(x) + lo(x), hi = RNE bf16 of x,
 // lo = RNE bf16 of the remainder, accumulated in FP32 by v_mfma_f32_16x16x16bf16_1k,
 // whose four k values per lane are the q = 0..3 of the FP32 form.  A is split
-// once into four bf16 planes (re/im x hi/lo) staged in LDS twice: row-major for
-// the forward product (four consecutive m per lane read) and transposed for the
+// once into four bf16 planes (re/im x hi/lo), each held twice: row-major for the
+// forward product (four consecutive m per lane read) and transposed for the
 // adjoint (four consecutive n per lane read), so the A operands are plain 8-byte
-// LDS loads; d and r are split per product with the hardware bf16 conversion.
+// loads; the planes are staged in LDS where they fit (ALDS) and otherwise read
+// from the copy the setup writes to the workspace, which stays in L2.  d and r
+// are split per product with the hardware bf16 conversion.
 //
 // Pixels retire when the FP32 KKT residual passes tol, or after fista_cap
 // iterations; a retired slot is refilled at once from a global atomic queue.
@@ -88,7 +90,7 @@ __device__ __forceinline__ s4 neg4(s4 v)
     u.y ^= 0x80008000u;
     return __builtin_bit_cast(s4, u);
 }
-__device__ __forceinline__ s4 lds4(const uint16_t *p) { return *reinterpret_cast<const s4 *>(p); }
+__device__ __forceinline__ s4 ld4(const uint16_t *p) { return *reinterpret_cast<const s4 *>(p); }
 
 // Sum / max over the four lanes (h = 0..3) that hold one pixel slot.
 __device__ __forceinline__ float sum_h(float v)
@@ -154,7 +156,6 @@ __host__ __device__ inline size_t fm_bf_planes_bytes(int rows, int l_pad)
 template <int T, int KB, bool ALDS, int PREC, int WMAX>
 __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 {
-    static_assert(PREC == L1LS_FP32 || ALDS, "split-BF16 stages its A planes in LDS");
     constexpr bool BF = PREC == L1LS_SPLIT_BF16;
     using fm::f4;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -170,10 +171,13 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 
     size_t off = 0;
     float2 *sA = reinterpret_cast<float2 *>(smem);
-    uint16_t *sF = reinterpret_cast<uint16_t *>(smem);  // split-BF16 planes [4][rows][ldf]
-    const int ldf = fm_bf_ldf(a.l_pad), lda = fm_bf_lda(rows);
-    uint16_t *sT = sF + (size_t)4 * rows * ldf;          // transposed planes [4][l_pad][lda]
-    if (BF) off = (fm_bf_planes_bytes(rows, a.l_pad) + 15) & ~(size_t)15;
+    // split-BF16 planes [4][rows][ldf] and transposed [4][l_pad][lda]: staged in LDS
+    // (ALDS) or read from the workspace copy the setup wrote (L2)
+    uint16_t *sF = reinterpret_cast<uint16_t *>(smem);
+    uint16_t *sT = sF + (size_t)4 * rows * fm_bf_ldf(a.l_pad);
+    const uint16_t *pF = ALDS ? sF : a.Abf, *pT = ALDS ? sT : a.Abf + (size_t)4 * rows * a.l_pad;
+    const int ldf = ALDS ? fm_bf_ldf(a.l_pad) : a.l_pad, lda = ALDS ? fm_bf_lda(rows) : rows;
+    if (BF && ALDS) off = (fm_bf_planes_bytes(rows, a.l_pad) + 15) & ~(size_t)15;
     else if (ALDS) off = ((size_t)rows * fm_lds_ld(a.l_pad) * sizeof(float2) + 15) & ~(size_t)15;
     f4 *sPW = reinterpret_cast<f4 *>(smem + off);   // [W][2T][64] forward partials
     off += (size_t)W * 2 * T * 64 * sizeof(f4);
@@ -190,7 +194,7 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
     float2 *sRp = reinterpret_cast<float2 *>(smem + off) + (size_t)W * KB * 4 * 64 + (size_t)w * T * 4 * 64 + lane;
 
     fm::AView Av;
-    if constexpr (BF) {
+    if constexpr (BF && ALDS) {
         // planes c = 0 re hi, 1 im hi, 2 re lo, 3 im lo
         for (int idx = tid; idx < rows * a.l_pad; idx += blockDim.x) {
             const int row = idx / a.l_pad, m = idx % a.l_pad;
@@ -444,10 +448,10 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
                     const int n0 = 16 * t + 4 * h;
-                    const fm::s4 arh = fm::lds4(sT + ((size_t)0 * a.l_pad + m) * lda + n0);
-                    const fm::s4 aih = fm::lds4(sT + ((size_t)1 * a.l_pad + m) * lda + n0);
-                    const fm::s4 arl = fm::lds4(sT + ((size_t)2 * a.l_pad + m) * lda + n0);
-                    const fm::s4 ail = fm::lds4(sT + ((size_t)3 * a.l_pad + m) * lda + n0);
+                    const fm::s4 arh = fm::ld4(pT + ((size_t)0 * a.l_pad + m) * lda + n0);
+                    const fm::s4 aih = fm::ld4(pT + ((size_t)1 * a.l_pad + m) * lda + n0);
+                    const fm::s4 arl = fm::ld4(pT + ((size_t)2 * a.l_pad + m) * lda + n0);
+                    const fm::s4 ail = fm::ld4(pT + ((size_t)3 * a.l_pad + m) * lda + n0);
                     // G_re += A_re (2 r_re) + A_im (2 r_im);  G_im += A_re (2 r_im) - A_im (2 r_re)
                     gr = fm::mfma_bf(arh, rrh[t], gr);
                     gr = fm::mfma_bf(arh, rrl[t], gr);
@@ -628,10 +632,10 @@ __device__ __forceinline__ void fista_mfma_stack(const FistaArgs &a)
 #pragma unroll
                     for (int t = 0; t < T; ++t) {
                         const int row = 16 * t + j;
-                        const fm::s4 arh = fm::lds4(sF + ((size_t)0 * rows + row) * ldf + m0);
-                        const fm::s4 aih = fm::lds4(sF + ((size_t)1 * rows + row) * ldf + m0);
-                        const fm::s4 arl = fm::lds4(sF + ((size_t)2 * rows + row) * ldf + m0);
-                        const fm::s4 ail = fm::lds4(sF + ((size_t)3 * rows + row) * ldf + m0);
+                        const fm::s4 arh = fm::ld4(pF + ((size_t)0 * rows + row) * ldf + m0);
+                        const fm::s4 aih = fm::ld4(pF + ((size_t)1 * rows + row) * ldf + m0);
+                        const fm::s4 arl = fm::ld4(pF + ((size_t)2 * rows + row) * ldf + m0);
+                        const fm::s4 ail = fm::ld4(pF + ((size_t)3 * rows + row) * ldf + m0);
                         // W_re += A_re d_re + A_im (-d_im);  W_im += A_im d_re + A_re d_im
                         Wr[t] = fm::mfma_bf(arh, drh, Wr[t]);
                         Wr[t] = fm::mfma_bf(arh, drl, Wr[t]);

@@ -31,6 +31,8 @@ struct FistaArgs {
     int64_t p;
     const float2 *A;          // packed: rows_pad_for(n) x l_pad, zero padded rows and columns
     const float2 *At;         // transposed: l_pad x n (At[m n + i] = A[i][m])
+    const uint16_t *Abf;      // split-BF16 planes (re hi, im hi, re lo, im lo) of the packed A:
+                              // [4][rows_pad][l_pad], then transposed [4][l_pad][rows_pad]
     const float2 *B;          // p x n
     const float *lambda;
     int64_t lambda_stride;
@@ -132,7 +134,7 @@ __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) / 256 * 
 
 // Workspace layout for one stack (byte offsets; every region 256-byte aligned).
 struct StackWorkspace {
-    size_t a_packed, a_trans, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid,
+    size_t a_packed, a_trans, a_bf16, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid,
         overflow, hgram, cbuf, total;
 };
 __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
@@ -144,6 +146,8 @@ __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, i
     off = ws_align(off + (size_t)rows_pad_for(n) * l_pad * sizeof(float2));
     w.a_trans = off;
     off = ws_align(off + (size_t)l_pad * n * sizeof(float2));
+    w.a_bf16 = off;  // split-BF16 planes of the packed A, row-major and transposed
+    off = ws_align(off + (size_t)2 * 4 * rows_pad_for(n) * l_pad * sizeof(uint16_t));
     w.gram = off;  // M = A A^H, then two N x N buffers for its repeated squares
     off = ws_align(off + (size_t)3 * n * n * sizeof(double2));
     w.consts = off;
@@ -224,6 +228,7 @@ __host__ __device__ inline FistaArgs fista_args_for(const StackDesc &d, const So
     fa.p = d.p;
     fa.A = (const float2 *)(d.ws + lay.a_packed);
     fa.At = (const float2 *)(d.ws + lay.a_trans);
+    fa.Abf = (const uint16_t *)(d.ws + lay.a_bf16);
     fa.B = d.B;
     fa.lambda = d.lambda;
     fa.lambda_stride = d.lambda_stride;

@@ -159,8 +159,7 @@ IterVariant autotune(int n, int l, const l1ls_options &opt, int dev)
     std::vector<std::pair<int, int>> cands;  // (choice, alt)
     IterVariant probe;
     for (int alt = 0; alt < 3; ++alt)
-        if (mfma_supports(n, l) && iter_variant(n, l, opt.precision, kMfma, alt, &probe) &&
-            !(opt.warm_start && probe.family == kVarEmbedded))
+        if (mfma_supports(n, l) && iter_variant(n, l, opt.precision, kMfma, alt, &probe))
             cands.push_back({kMfma, alt});
     if (opt.precision == L1LS_FP32) cands.push_back({kWave, 0});  // the wave kernel is FP32 only
     IterVariant best_v;
@@ -257,10 +256,6 @@ l1ls_status l1ls_plan_create(const l1ls_stack *stacks, int32_t count, const l1ls
             it.var = autotune(it.n, it.l, *opt, pl->device);
         } else {
             iter_variant(it.n, it.l, opt->precision, kAuto, 0, &it.var);
-        }
-        if (opt->warm_start && it.var.family == kVarEmbedded) {
-            delete pl;
-            return set_error(L1LS_ERR_UNSUPPORTED_SHAPE, "warm_start with split-BF16 needs l <= 256 (stack %d)", i);
         }
         l1ls_workspace_size(it.n, it.l, it.p, opt, &it.ws_bytes);
         it.ws_off = off;

@@ -97,14 +97,10 @@ def test_noalloc_size_limit_checked_on_host(L):
 
 
 def test_warm_start_refused_where_unsupported(L):
-    # Algorithm 1 from X runs in the split re/im MFMA kernels and the wave kernel:
-    # split-BF16 with l > 256 and the block form refuse it before any launch
+    # Algorithm 1 from X runs in the split re/im MFMA kernels and the wave kernel;
+    # the block form refuses it before any launch
     o = L.l1ls_options_default()
     o.warm_start = 1
-    o.precision = 1
-    assert _solve(L, n=4, l=512, o=o, wsb=1 << 26) == -2
-    assert b"warm_start" in L.l1ls_last_error()
-    o.precision = 0
     st = L.l1ls_solve_blocks(4, 8, 3, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(64), 0,
                              ctypes.byref(o), 2, ctypes.c_void_p(512), ctypes.c_void_p(128), None,
                              ctypes.c_void_p(256), 1 << 20, None)

@@ -53,10 +53,13 @@ def test_golden_warm_trajectory_on_device(dev, precision, rtol):
         assert (d["iters"].cpu().numpy() == r["k"]).all()
 
 
-@pytest.mark.parametrize("n,l,p", [(15, 101, 512), (25, 256, 256), (70, 300, 96)])
-def test_warm_trajectory_parity(dev, orc, n, l, p):
+@pytest.mark.parametrize("n,l,p,precision", [(15, 101, 512, "fp32"), (25, 256, 256, "fp32"), (70, 300, 96, "fp32"),
+                                             (25, 256, 256, "split_bf16"), (40, 200, 128, "split_bf16"),
+                                             (50, 512, 128, "split_bf16")])
+def test_warm_trajectory_parity(dev, orc, n, l, p, precision):
     """Five iterations from x^(0) = the oracle's third iterate from 0 (complex64): device
-    (MFMA kernel for n <= 64, wave kernel above) against the oracle from the same x^(0)."""
+    (MFMA kernel for n <= 64, wave kernel above; split-BF16 with A's planes in LDS or
+    read from L2) against the oracle from the same x^(0)."""
     A32, B32, l32 = _stack(n, l, p)
     A64, B64, L64 = A32.astype(np.complex128), B32.astype(np.complex128), l32.astype(np.float64)
     X3, _ = orc.rbpg_batch(A64, B64, L64, tol=1e-30, max_iter=3)
@@ -64,7 +67,7 @@ def test_warm_trajectory_parity(dev, orc, n, l, p):
     print(f"warm trajectory n={n} l={l} p={p}", flush=True)
     X = _t(dev, X0)
     _, d = api.solve(_t(dev, A32), _t(dev, B32), _t(dev, l32), out=X, warm_start=True, max_iter=5,
-                     tol=1e-30, fp64_polish=0)
+                     tol=1e-30, fp64_polish=0, precision=precision)
     Xo, do = orc.rbpg_batch(A64, B64, L64, tol=1e-30, max_iter=5, X0=X0.astype(np.complex128))
     Xg = X.cpu().numpy().astype(np.complex128)
     Lf = orc.lipschitz(A64)
@@ -74,8 +77,10 @@ def test_warm_trajectory_parity(dev, orc, n, l, p):
     Xc, _ = orc.rbpg_batch(A64, B64, L64, tol=1e-30, max_iter=5)
     ec = np.linalg.norm(Xc - Xo, axis=1) / den
     print(f"  e median {np.median(e):.1e}, e <= 1e-4 {np.mean(e <= 1e-4):.3f}; cold differs {np.median(ec):.1e}")
-    assert np.median(e) < 1e-6
-    assert (e <= 1e-4).mean() >= 0.98
+    # split-BF16 products carry about 2^-16 relative error each (three bf16 passes)
+    med, bar = (1e-6, 1e-4) if precision == "fp32" else (3e-5, 1e-3)
+    assert np.median(e) < med
+    assert (e <= bar).mean() >= 0.98
     assert np.median(ec) > 1e-3
     # iterations performed agree (an FP32 iterate can land exactly on its fixed point,
     # which the tol = 1e-30 test then reports converged a step early)
@@ -118,10 +123,7 @@ def test_warm_solve_from_perturbed_minimiser(dev, orc, n, l, p):
     assert d["iters"].float().mean().item() < dc["iters"].float().mean().item()
 
 
-def test_warm_start_refusals(dev):
+def test_warm_start_needs_out(dev):
     A32, B32, l32 = _stack(20, 400, 8)
-    X = torch.zeros((8, 400), dtype=torch.complex64, device=dev)
-    with pytest.raises(_lib.L1LSError, match="UNSUPPORTED"):
-        api.solve(_t(dev, A32), _t(dev, B32), _t(dev, l32), out=X, warm_start=True, precision="split_bf16")
     with pytest.raises(ValueError):
         api.solve(_t(dev, A32), _t(dev, B32), _t(dev, l32), warm_start=True)
