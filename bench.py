@@ -52,7 +52,6 @@ SUPERRES_REALISATIONS = 5000
 KERNEL_SOURCES = {
     "fista_mfma_kernel": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
     "fista_mfma_kernel_bf16": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
-    "fista_kernel": ("fista_impl.h", "fista.hip", "l1ls_internal.h"),
     "fista_wave_kernel": ("fista_wave.hip", "l1ls_internal.h"),
     "polish_kernel": ("polish.hip", "wave_reduce.h", "l1ls_internal.h"),
     "certify_kernel": ("certify.hip", "wave_reduce.h", "l1ls_internal.h"),
@@ -404,8 +403,7 @@ def rooflines(r, n, l, prec, workload, polish):
         if prec == "fp32":
             it_kernel = "fista_mfma_kernel"
         else:
-            # split-BF16 with 256 < L runs the real-embedded kernel (its A planes do not fit LDS)
-            it_kernel = "fista_mfma_kernel_bf16" if l <= 256 else "fista_kernel"
+            it_kernel = "fista_mfma_kernel_bf16"
     else:
         it_kernel = "fista_wave_kernel"
     # iteration kernel: algorithmic flops = (forward + adjoint products) x 8 N L

@@ -6,8 +6,6 @@
 
 namespace l1ls {
 
-template <int NZB, int KB, bool ALDS, int PREC>
-hipError_t launch_one(const FistaArgs &a, int max_groups, hipStream_t s);
 template <int T, int KB, bool ALDS, int PREC, int WMAX>
 hipError_t launch_mfma_one(const StackTable &t, int waves, hipStream_t s);
 size_t fm_bf_planes_bytes_host(int rows, int l_pad);
@@ -282,49 +280,9 @@ hipError_t launch_setup_table(const StackTable &t, bool bin_gram, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 
-size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds)
-{
-    size_t off = a_lds ? (((size_t)n * (l_pad + 4) * sizeof(float2) + 15) & ~(size_t)15) : 0;
-    off += (size_t)waves * zb * 64 * 16;
-    off += (size_t)waves * 16 * 16;
-    off += 16;
-    return off;
-}
-
-bool fista_a_fits_lds(int n, int l_pad, int waves, int zb)
-{
-    // one wave per SIMD: a workgroup of W waves may use W/4 of the CU's 160 KB
-    return fista_lds_bytes(n, l_pad, waves, zb, true) <= (size_t)160 * 1024 * waves / 4;
-}
-
-template <int NZB, int PREC>
-static hipError_t launch_zb(const FistaArgs &a, int max_groups, hipStream_t s)
-{
-    const bool lds = fista_a_fits_lds(a.n, a.l_pad, a.waves, NZB);
-    if (slice_blocks_for(a.l) == 8)
-        return lds ? launch_one<NZB, 8, true, PREC>(a, max_groups, s)
-                   : launch_one<NZB, 8, false, PREC>(a, max_groups, s);
-    return lds ? launch_one<NZB, 16, true, PREC>(a, max_groups, s)
-               : launch_one<NZB, 16, false, PREC>(a, max_groups, s);
-}
-
-template <int PREC>
-static hipError_t launch_prec(const FistaArgs &a, int max_groups, hipStream_t s)
-{
-    switch (zblocks_for(a.n)) {
-    case 1: return launch_zb<1, PREC>(a, max_groups, s);
-    case 2: return launch_zb<2, PREC>(a, max_groups, s);
-    case 3: return launch_zb<3, PREC>(a, max_groups, s);
-    case 4: return launch_zb<4, PREC>(a, max_groups, s);
-    case 5: return launch_zb<5, PREC>(a, max_groups, s);
-    case 6: return launch_zb<6, PREC>(a, max_groups, s);
-    case 7: return launch_zb<7, PREC>(a, max_groups, s);
-    case 8: return launch_zb<8, PREC>(a, max_groups, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-// FP32 contractions: the kernel with split real/imaginary accumulators
+// LDS of the split re/im MFMA kernel: A (FP32, or its four split-BF16 planes
+// twice) where staged, the cross-wave partials, and at 128 unknowns a wave the
+// LDS-held iteration state
 size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precision)
 {
     const int rows = rows_pad_for(n), T = rows / 16;
@@ -355,8 +313,8 @@ bool mfma_supports(int n, int l);
 // The tiling a stack runs (see IterVariant).  FP32: up to 32 rows and 256 bins a
 // wave holds 32 unknowns and a workgroup up to eight waves (two per SIMD), else 64
 // (L <= 256) or 128 unknowns a wave and up to four waves; A is staged in LDS
-// where it fits.  Split-BF16 stages its bf16 planes of A in LDS (L <= 256) or
-// runs the real-embedded kernel.  Shapes beyond the MFMA kernels (N > 64 or
+// where it fits.  Split-BF16 stages its bf16 planes of A in LDS where they fit,
+// else reads them from L2.  Shapes beyond the MFMA kernels (N > 64 or
 // L > 512), or choice kWave, run the wave-per-pixel kernel.
 bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant *v)
 {
@@ -410,8 +368,7 @@ bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant 
 size_t iter_variant_lds(const IterVariant &v, int n, int l)
 {
     if (v.family == kVarWave) return fista_wave_lds(n, l);
-    if (v.family == kVarMfma) return fista_mfma_lds_bytes(n, lpad_for(l), v.waves, v.alds != 0, v.prec);
-    return fista_lds_bytes(n, lpad_for(l), v.waves, v.T, v.alds != 0);
+    return fista_mfma_lds_bytes(n, lpad_for(l), v.waves, v.alds != 0, v.prec);
 }
 
 template <int T, int PREC>
@@ -439,21 +396,10 @@ static hipError_t launch_mfma_t(const StackTable &t, const IterVariant &v, hipSt
     }
 }
 
-// One launch for the stacks of a table that all run variant v (the
-// real-embedded kernel takes one stack per launch).
+// One launch for the stacks of a table that all run variant v.
 hipError_t launch_iteration_table(const StackTable &t, const IterVariant &v, hipStream_t s)
 {
     if (v.family == kVarWave) return launch_wave_table(t, v.nc, s);
-    if (v.family == kVarEmbedded) {
-        for (int i = 0; i < t.count; ++i) {
-            if (t.d[i].p <= 0) continue;
-            const FistaArgs a = fista_args_for(t.d[i], t.o);
-            if (a.warm) return hipErrorNotSupported;
-            const hipError_t e = launch_prec<L1LS_SPLIT_BF16>(a, 0, s);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    }
     const bool bf = v.prec == L1LS_SPLIT_BF16;
     switch (v.T) {
     case 1: return bf ? launch_mfma_t<1, L1LS_SPLIT_BF16>(t, v, s) : launch_mfma_t<1, L1LS_FP32>(t, v, s);

@@ -326,7 +326,7 @@ hipError_t launch_polish_wide_table(const StackTable &t, hipStream_t s);  // 32 
 // blocks, KB unknown blocks per wave, A staged in LDS or read from L2, up to
 // WMAX waves of which `waves` run), or the wave-per-pixel kernel (NC chunks).
 struct IterVariant {
-    int family;   // kVarMfma, kVarWave, kVarEmbedded (real-embedded, one stack per launch)
+    int family;   // kVarMfma, kVarWave
     int T, KB, alds, prec, wmax, waves, nc;
     bool operator==(const IterVariant &o) const
     {
@@ -334,7 +334,7 @@ struct IterVariant {
                wmax == o.wmax && waves == o.waves && nc == o.nc;
     }
 };
-enum { kVarMfma = 1, kVarWave = 2, kVarEmbedded = 3 };
+enum { kVarMfma = 1, kVarWave = 2 };
 // The default variant for a shape and precision (kMfma: the MFMA families, kWave:
 // the wave kernel); `alt` selects an alternative tiling for the autotuner
 // (0 default, 1 the other A placement, 2 the other unknowns-per-wave split);
@@ -378,8 +378,6 @@ hipError_t launch_unrolled_backward(int n, int l, int64_t p, const float2 *B, fl
                                     float alpha, int K, int ckpt, const void *tape,
                                     const float2 *dX, float2 *dB, float *dlambda, float *dxi,
                                     void *ws, hipStream_t st);
-size_t fista_lds_bytes(int n, int l_pad, int waves, int zb, bool a_lds);
 size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precision);
-bool fista_a_fits_lds(int n, int l_pad, int waves, int zb);
 
 }  // namespace l1ls

@@ -328,7 +328,7 @@ int32_t l1ls_plan_describe(const l1ls_plan *plan, char *buf, int32_t buf_len)
                      (long long)it.p, v.nc);
         else
             snprintf(line, sizeof line, "stack %zu: n=%d l=%d p=%lld kernel=%s T=%d KB=%d waves=%d A=%s\n", i, it.n,
-                     it.l, (long long)it.p, v.family == kVarMfma ? "mfma" : "embedded", v.T, v.KB, v.waves,
+                     it.l, (long long)it.p, "mfma", v.T, v.KB, v.waves,
                      v.alds ? "lds" : "l2");
         s += line;
     }

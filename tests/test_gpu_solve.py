@@ -278,8 +278,8 @@ def test_split_bf16_exact_mode(c1):
 
 @pytest.mark.parametrize("n,l,p", [(3, 7, 17), (25, 256, 40), (40, 200, 24), (64, 256, 16), (50, 512, 12)])
 def test_split_bf16_ragged_shapes(dev, orc, n, l, p):
-    """Split-BF16 iteration on every kernel family it uses (bf16 planes in LDS for
-    L <= 256, the real-embedded form above), refined in FP64: objective at the
+    """Split-BF16 iteration on every tiling it uses (bf16 planes of A in LDS up to
+    32 rows at L <= 256, read from L2 otherwise), refined in FP64: objective at the
     certified minimiser and every pixel converged."""
     geom = synth.make_geometry(9, n, l, 250.0, -50.0, 50.0)
     spec = synth.Spec(9, n, l, p, 250.0, -50.0, 50.0, "c1", 10.0)
