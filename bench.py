@@ -61,16 +61,19 @@ PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s
 # oracle pixels per workload: Algorithm 1 timed (cpu_baseline) and the certified
 # minimiser for the parity sample (strided over the whole stack); about 10-30 s
 # of host work each on 16 cores
-CPU_SAMPLE = {"scene": 16384, "pairs": 1024, "tiny": 1024, "motion": 4096, "motion_fine": 2048,
+CPU_SAMPLE = {"scene": 16384, "pairs": 4096, "tiny": 1024, "motion": 4096, "motion_fine": 2048,
               "superres": 16384}
 PARITY_SAMPLE = {"scene": 1024, "pairs": 512, "tiny": 1024, "motion": 512, "motion_fine": 256,
                  "superres": 960}
 PARITY_BAR = {"fp32": 1e-4, "split_bf16": 1e-3}
 POLISH_AFTER = 12          # FP32 iterations before a pixel goes to the FP64 stage
 # per workload where another budget is faster (measured with every pixel refined:
-# close pairs 2.46 / 2.60 / 2.61 / 2.62 M solved pixels/s at 12 / 8 / 6 / 4; the
-# scene is fastest at 12)
-POLISH_AFTER_BY_WORKLOAD = {"pairs": 6}
+# close pairs 4.83 / 4.71 / 4.57 / 4.32 / 4.08 / 3.86 M solved pixels/s at
+# 2 / 3 / 4 / 6 / 8 / 10).  Below 4 the FP32 stage is hardly an estimate of the
+# solution any more (its step search has barely started) and the FP32 against
+# split-BF16 comparison vanishes into the refinement, so 4 is kept; the scene
+# 12.84 / 13.53 / 13.55 / 13.82 M at 12 / 8 / 6 / 4, 8 kept for the same reason.
+POLISH_AFTER_BY_WORKLOAD = {"pairs": 4, "scene": 8}
 
 
 def polish_after_for(workload: str) -> int:
@@ -396,6 +399,30 @@ def run_precision(api, Ad, Bd, ld, X, ws, n, l, p, prec, steps, warmup, args, sa
             "X_host": x_host}
 
 
+def algorithm1_only(api, Ad, Bd, ld, X, n, l, args):
+    """One FP32 solve by Algorithm 1 alone (fp64_polish = 0, max_iter iterations)."""
+    import torch
+    p = Bd.shape[0]
+    ws = api.Workspace()
+    opts = dict(max_iter=args.max_iter, tol=1e-4, precision="fp32", fp64_polish=0, polish_after=0)
+    api.timing_enable(True)
+    for kc in ("iteration", "refine", "certify"):
+        api.timing_read(kc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, d = api.solve(Ad, Bd.contiguous(), ld.contiguous(), out=X, workspace=ws, **opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it_ms, _ = api.timing_read("iteration")
+    api.timing_enable(False)
+    solved = int(((d["status"] & 1) != 0).sum().item())
+    iters = d["iters"].float()
+    return {"pixels": p, "value": solved / dt, "unit": "pixels/s", "solved_fraction": solved / p,
+            "ms": dt * 1e3, "iteration_ms": it_ms, "mean_iterations": float(iters.mean().item()),
+            "max_iter": args.max_iter,
+            "note": "Algorithm 1 in FP32 on the MFMA kernel, no FP64 refinement; FP64 certificate"}
+
+
 def rooflines(r, n, l, prec, workload, polish):
     """Roofline objects of the iteration and refinement kernels of one run."""
     avg_s = r["avg_s"]
@@ -454,6 +481,8 @@ def main():
                     help="pixels of the parity report (-1: the workload's default, 0: none)")
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--alg1-pixels", type=int, default=1 << 20,
+                    help="pixels of the Algorithm-1-only leg (0: skip it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -569,6 +598,12 @@ def main():
         rec["compare"] = {"precision": "split_bf16", "value": None,
                           "note": f"not available at n = {n}, l = {l}: split-BF16 runs in the MFMA "
                                   f"kernels only (n <= 64, l <= 512)"}
+    # Algorithm 1 alone (FP32, up to max_iter iterations, no FP64 refinement; the
+    # certificate still decides "solved") on the first pixels, for context: the
+    # value above comes from a short Algorithm 1 stage plus the FP64 refinement
+    if args.alg1_pixels > 0:
+        p1 = min(p, args.alg1_pixels)
+        rec["algorithm1_only"] = algorithm1_only(api, Ad[:], Bd[:p1], ld[:p1], X[:p1], n, l, args)
     # the oracle leg (after all GPU timing): Algorithm 1 timed on the host cores,
     # and the certified minimisers of the parity sample
     if not args.no_cpu_baseline:

@@ -135,10 +135,27 @@ __device__ void residual_start(const PolishArgsDev &a, PolishShared &sh, const f
         if (lane == 0) sh.cnt = base + __popcll(bal);
         __syncthreads();
     }
+    // r = A x0 - b over the listed bins in list order, eight bins' loads in flight
+    // (the FP32 iterate handed over can have hundreds of nonzeros)
     const int cnt = sh.cnt;
     for (int nn = lane; nn < a.n; nn += 64) {
         double rr = -(double)b[nn].x, ri = -(double)b[nn].y;
-        for (int q = 0; q < cnt; ++q) {
+        int q = 0;
+        for (; q + 8 <= cnt; q += 8) {
+            float2 xf[8], af[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int m = sh.nzl[q + u];
+                xf[u] = x0[m];
+                af[u] = a.A[(size_t)nn * a.l_pad + m];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                rr += (double)af[u].x * xf[u].x - (double)af[u].y * xf[u].y;
+                ri += (double)af[u].x * xf[u].y + (double)af[u].y * xf[u].x;
+            }
+        }
+        for (; q < cnt; ++q) {
             const int m = sh.nzl[q];
             const float2 xf = x0[m];
             const double2 av = Aat(a, nn, m);
