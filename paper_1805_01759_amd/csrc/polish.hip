@@ -405,27 +405,7 @@ __device__ void gram_pass(const PolishArgsDev &a, PolishShared &sh, const double
     for (int t = lane; t < s; t += 64) l1 += sqrt(sh.z[t].x * sh.z[t].x + sh.z[t].y * sh.z[t].y);
     const double tau = lam * inv_lf, tau2 = tau * tau;
     const double lv = lam * (1.0 + 1e-12), lv2 = lv * lv;
-    for (int m = lane; m < a.l; m += 64) {
-        const double2 cm = cb[m];
-        double gr = -cm.x, gi = -cm.y;
-        int t = 0;
-        for (; t + 4 <= s; t += 4) {
-            double2 hv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) hv[u] = a.H[(size_t)sh.S[t + u] * a.l + m];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double2 zv = sh.z[t + u];
-                gr += hv[u].x * zv.x + hv[u].y * zv.y;  // conj(H[S_t][m]) z_t
-                gi += hv[u].x * zv.y - hv[u].y * zv.x;
-            }
-        }
-        for (; t < s; ++t) {
-            const double2 hv = a.H[(size_t)sh.S[t] * a.l + m];
-            const double2 zv = sh.z[t];
-            gr += hv.x * zv.x + hv.y * zv.y;
-            gi += hv.x * zv.y - hv.y * zv.x;
-        }
+    auto bin_done = [&](int m, double gr, double gi) {
         const int ts = sh.sidx[m];
         const double2 v = ts >= 0 ? sh.z[ts] : make_double2(0.0, 0.0);
         const double xr = v.x, xi = v.y;
@@ -444,6 +424,40 @@ __device__ void gram_pass(const PolishArgsDev &a, PolishShared &sh, const double
             vbest = gm2;
             vidx = m;
         }
+    };
+    // two bins a lane (m0, m0 + 64) and four working-set rows per batch: the pass
+    // is latency bound on the rows of H (4 MB at L = 512, beyond one XCD's L2), so
+    // a batch's eight loads are issued before any is used (eight rows a batch
+    // spill more and measured slower)
+    for (int m0 = lane; m0 < a.l; m0 += 128) {
+        const int m1 = m0 + 64;
+        const bool two = m1 < a.l;
+        const int m1c = two ? m1 : m0;
+        const double2 c0 = cb[m0], c1 = cb[m1c];
+        double gr0 = -c0.x, gi0 = -c0.y, gr1 = -c1.x, gi1 = -c1.y;
+        for (int t0 = 0; t0 < s; t0 += 4) {
+            double2 h0[4], h1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (t0 + u < s) {
+                    const size_t row = (size_t)sh.S[t0 + u] * a.l;
+                    h0[u] = a.H[row + m0];
+                    h1[u] = a.H[row + m1c];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (t0 + u < s) {
+                    const double2 zv = sh.z[t0 + u];  // conj(H[S_t][m]) z_t
+                    gr0 += h0[u].x * zv.x + h0[u].y * zv.y;
+                    gi0 += h0[u].x * zv.y - h0[u].y * zv.x;
+                    gr1 += h1[u].x * zv.x + h1[u].y * zv.y;
+                    gi1 += h1[u].x * zv.y - h1[u].y * zv.x;
+                }
+            }
+        }
+        bin_done(m0, gr0, gi0);
+        if (two) bin_done(m1, gr1, gi1);
     }
     pass_finish<false>(sh, acc, l1, km, vbest, lam, lf, F, kk, vidx);
 }
