@@ -127,13 +127,27 @@ __device__ __forceinline__ void certify_pixel(const CertifyArgs &a, int64_t p, f
     }
 }
 
+// LDS of a workgroup for a table: x and its nonzero list (l_pad entries each)
+// and r (n entries), sized for the largest stack of the table.
+__host__ __device__ inline size_t certify_lds(int lp, int nm)
+{
+    return (size_t)lp * sizeof(float2) + (size_t)nm * sizeof(double2) + (size_t)lp * sizeof(int16_t);
+}
+
 // One workgroup a pixel for up to 2^25 pixels a stack, grid-stride beyond (the
 // grid stays within the dispatch limits at any pixel count); stacks in table order.
 __global__ void __launch_bounds__(64) certify_kernel(const StackTable t)
 {
-    __shared__ float2 sx[64 * kMaxWaves];
-    __shared__ double2 sr[kMaxN];
-    __shared__ int16_t snz[64 * kMaxWaves];
+    extern __shared__ __align__(16) unsigned char cdyn[];
+    int lp = 64, nm = 1;
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        lp = lp > lpad_for(t.d[i].l) ? lp : lpad_for(t.d[i].l);
+        nm = nm > t.d[i].n ? nm : t.d[i].n;
+    }
+    float2 *sx = reinterpret_cast<float2 *>(cdyn);
+    double2 *sr = reinterpret_cast<double2 *>(cdyn + (size_t)lp * sizeof(float2));
+    int16_t *snz = reinterpret_cast<int16_t *>(cdyn + (size_t)lp * sizeof(float2) + (size_t)nm * sizeof(double2));
     for (int i = 0; i < t.count; ++i) {
         if (t.d[i].p <= 0) continue;
         const CertifyArgs a = certify_args_for(t.d[i], t.o);
@@ -147,10 +161,16 @@ __global__ void __launch_bounds__(64) certify_kernel(const StackTable t)
 hipError_t launch_certify_table(const StackTable &t, hipStream_t s)
 {
     int64_t g = 0;
-    for (int i = 0; i < t.count; ++i) g = t.d[i].p > g ? t.d[i].p : g;
+    int lp = 64, nm = 1;
+    for (int i = 0; i < t.count; ++i) {
+        if (t.d[i].p <= 0) continue;
+        g = t.d[i].p > g ? t.d[i].p : g;
+        lp = lp > lpad_for(t.d[i].l) ? lp : lpad_for(t.d[i].l);
+        nm = nm > t.d[i].n ? nm : t.d[i].n;
+    }
     if (g == 0) return hipSuccess;
     if (g > ((int64_t)1 << 25)) g = (int64_t)1 << 25;
-    hipLaunchKernelGGL(certify_kernel, dim3((unsigned)g), dim3(64), 0, s, t);
+    hipLaunchKernelGGL(certify_kernel, dim3((unsigned)g), dim3(64), certify_lds(lp, nm), s, t);
     return hipGetLastError();
 }
 
