@@ -367,7 +367,7 @@ def run_precision(api, Ad, Bd, ld, X, ws, n, l, p, prec, steps, warmup, args, sa
     the last solve (x and the CONVERGED bit) for the parity report."""
     import torch
     opts = dict(max_iter=args.max_iter, tol=1e-4, precision=prec, fp64_polish=args.polish,
-                polish_after=args.polish_after)
+                polish_after=args.polish_after, fp64_continue=args.fp64_continue)
     for _ in range(warmup):
         api.solve(Ad, Bd, ld, out=X, workspace=ws, **opts)
     torch.cuda.synchronize()
@@ -481,6 +481,8 @@ def main():
                     help="pixels of the parity report (-1: the workload's default, 0: none)")
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-continue", action="store_true",
+                    help="pixels the 32-slot refinement leaves above tol continue Algorithm 1 in FP64")
     ap.add_argument("--alg1-pixels", type=int, default=1 << 20,
                     help="pixels of the Algorithm-1-only leg (0: skip it)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -566,6 +568,7 @@ def main():
         "config": {"workload": desc if not args.pixels else desc + f" (first {p} pixels)", "n": n, "l": l,
                    "pixels": p, "max_iter": args.max_iter, "tol": 1e-4, "precision": args.precision,
                    "polish_after": args.polish_after, "fp64_polish": args.polish,
+                   "fp64_continue": int(args.fp64_continue),
                    "solved_fraction": r["solved_fraction"], "pixels_refined_fp64": r["npol"],
                    "kernel_ms": {kc: v * 1e3 for kc, v in r["avg_s"].items()}},
         "roofline": roof,

@@ -93,6 +93,12 @@ typedef struct {
                               initial point x^(0) on entry (the Init of Algorithm 1; x^(1) =
                               x^(0), the step starts at alpha_0).  Not available in
                               l1ls_solve_blocks (L1LS_ERR_UNSUPPORTED_SHAPE)                 */
+    int32_t fp64_continue; /* 1: a pixel the refinement leaves above tol (its minimiser has more
+                              nonzeros than the 32-slot working set holds, or the active-set
+                              walk stalls) continues Algorithm 1 in FP64 from the best point
+                              found, until KKT <= tol or max_iter iterations in all (FP32 and
+                              FP64 counted together); needs fp64_polish.  0 (default): such a
+                              pixel is returned unsolved                                    */
 } l1ls_options;
 
 /* Device arrays of length P; any may be NULL.

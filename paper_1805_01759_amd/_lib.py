@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_float), ("c_alpha", ctypes.c_float),
                 ("precision", ctypes.c_int32), ("backtracking", ctypes.c_int32),
                 ("monotone", ctypes.c_int32), ("fp64_polish", ctypes.c_int32),
-                ("polish_after", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+                ("polish_after", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("fp64_continue", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):

@@ -23,7 +23,8 @@ def _stream(stream=None):
 
 
 def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracking=True,
-            monotone=True, fp64_polish=1, polish_after=0, warm_start=False) -> _lib.Options:
+            monotone=True, fp64_polish=1, polish_after=0, warm_start=False,
+            fp64_continue=False) -> _lib.Options:
     o = _lib.load().l1ls_options_default()
     o.max_iter = int(max_iter)
     o.tol = float(tol)
@@ -34,6 +35,7 @@ def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracki
     o.fp64_polish = int(fp64_polish)  # 0 off, 1 pixels above tol, 2 every pixel
     o.polish_after = int(polish_after)
     o.warm_start = int(bool(warm_start))  # X (out) holds the initial points on entry
+    o.fp64_continue = int(bool(fp64_continue))  # FP64 Algorithm 1 after the refinement
     return o
 
 

@@ -52,6 +52,8 @@ l1ls_status check_options(const l1ls_options *o)
     if (o->precision != L1LS_FP32 && o->precision != L1LS_SPLIT_BF16)
         return fail(L1LS_ERR_INVALID_ARG, "unknown precision %d", o->precision);
     if (o->warm_start != 0 && o->warm_start != 1) return fail(L1LS_ERR_INVALID_ARG, "warm_start must be 0 or 1");
+    if (o->fp64_continue != 0 && o->fp64_continue != 1)
+        return fail(L1LS_ERR_INVALID_ARG, "fp64_continue must be 0 or 1");
     if (o->fp64_polish < 0 || o->fp64_polish > 2)
         return fail(L1LS_ERR_INVALID_ARG, "fp64_polish must be 0, 1 or 2");
     return L1LS_OK;
@@ -122,6 +124,8 @@ SolveOpts solve_opts(const l1ls_options *opt)
     o.monotone = opt->monotone ? 1 : 0;
     o.polish = opt->fp64_polish;
     o.warm = opt->warm_start;
+    o.max_iter = opt->max_iter;
+    o.cont = opt->fp64_continue && opt->fp64_polish ? 1 : 0;
     return o;
 }
 
@@ -227,6 +231,8 @@ l1ls_status run_stacks(const StackDesc *d, const IterVariant *var, int count, co
         // recomputed)
         if (e == hipSuccess) e = chunks([&](const StackTable &t) { return launch_polish_mid_table(t, s); });
         if (e == hipSuccess) e = chunks([&](const StackTable &t) { return launch_polish_wide_table(t, s); });
+        // what the 32-slot pass leaves above tol: Algorithm 1 in FP64 (fp64_continue)
+        if (e == hipSuccess) e = chunks([&](const StackTable &t) { return launch_continue_table(t, s); });
         if (e != hipSuccess) return fail(L1LS_ERR_HIP, "refinement launch: %s", hipGetErrorString(e));
     }
     {
@@ -286,6 +292,7 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
         e = launch_polish_table(t, s);
         if (e == hipSuccess) e = launch_polish_mid_table(t, s);
         if (e == hipSuccess) e = launch_polish_wide_table(t, s);
+        if (e == hipSuccess) e = launch_continue_table(t, s);
         if (e != hipSuccess) return fail(L1LS_ERR_HIP, "refinement launch: %s", hipGetErrorString(e));
     }
     {
@@ -345,6 +352,7 @@ l1ls_options l1ls_options_default(void)
     o.fp64_polish = 1;
     o.polish_after = 0;
     o.warm_start = 0;
+    o.fp64_continue = 0;
     return o;
 }
 

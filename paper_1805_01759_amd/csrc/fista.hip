@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) setup_power_kernel(const StackTable t)
     __shared__ double2 v[kMaxN];
     __shared__ double2 wv[kMaxN];
     const int tid = threadIdx.x, bd = blockDim.x;
-    if (tid < 8) queue[tid] = 0u;
+    if (tid < 16) queue[tid] = 0u;
     if (tid < 4) work[tid] = 0ull;
     double cm = 0.0;
     for (int c = tid; c < l; c += bd) {

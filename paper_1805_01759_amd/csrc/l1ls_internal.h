@@ -153,7 +153,7 @@ __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, i
     w.consts = off;
     off = ws_align(off + sizeof(StackConsts));
     w.queue = off;
-    off = ws_align(off + 8 * sizeof(uint32_t));
+    off = ws_align(off + 16 * sizeof(uint32_t));
     w.work = off;
     off = ws_align(off + 4 * sizeof(unsigned long long));
     w.status = off;
@@ -206,7 +206,9 @@ struct SolveOpts {
     int32_t fista_cap;        // retire unsolved pixels after this many iterations
     float tol, c_alpha;
     int32_t backtracking, monotone, polish, warm;
-    int32_t pad;
+    int32_t max_iter;         // iterations of Algorithm 1 in all (the FP64 continuation's budget)
+    int32_t cont;             // 1: FP64 continuation of the pixels the refinement leaves above tol
+    int32_t pad[2];
 };
 constexpr int kMaxStacksPerLaunch = 32;
 struct StackTable {
@@ -273,11 +275,14 @@ __host__ __device__ inline PolishArgsDev polish_args_for(const StackDesc &d, con
     pa.X = d.X;
     pa.consts = (const StackConsts *)(d.ws + lay.consts);
     pa.count = queue + 1 + 2 * tier;  // counts in queue[1], [3], [5]; next pixel in [2], [4], [6]
+                                      // (the FP64 continuation: [7], [8])
     pa.next = queue + 2 + 2 * tier;
     pa.list = tier == 1 ? oflow : plist;
     pa.R = (tier == 0 && d.keep_residual) ? (const float2 *)(d.ws + lay.resid) : nullptr;
-    pa.overflow = tier == 0 ? oflow : (tier == 1 ? plist : nullptr);
-    pa.overflow_count = tier < 2 ? queue + 3 + 2 * tier : nullptr;
+    // tier 2 lists the pixels it leaves above tol for the FP64 continuation
+    // (queue[7]), when that runs
+    pa.overflow = tier == 0 ? oflow : (tier == 1 ? plist : (o.cont ? oflow : nullptr));
+    pa.overflow_count = tier < 2 || o.cont ? queue + 3 + 2 * tier : nullptr;
     pa.status = (uint32_t *)(d.ws + lay.status);
     pa.work = (unsigned long long *)(d.ws + lay.work);
     pa.H = (const double2 *)(d.ws + lay.hgram);
@@ -321,6 +326,7 @@ hipError_t launch_certify_table(const StackTable &t, hipStream_t s);
 hipError_t launch_polish_table(const StackTable &t, hipStream_t s);       // 8 slots
 hipError_t launch_polish_mid_table(const StackTable &t, hipStream_t s);   // 16 slots
 hipError_t launch_polish_wide_table(const StackTable &t, hipStream_t s);  // 32 slots
+hipError_t launch_continue_table(const StackTable &t, hipStream_t s);     // FP64 Algorithm 1
 
 // The iteration kernel that runs a stack: the split re/im MFMA tile (T row
 // blocks, KB unknown blocks per wave, A staged in LDS or read from L2, up to

@@ -868,6 +868,7 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
         // z += t d by r += t A_S d, c += t G d and the change the line search
         // measured, a drop or an entry by the column's rank-one term.
         bool fresh = true;
+        double kfin = 1e300;  // KKT residual of the last round-end pass
         // Newton on a working set stops at gstop, except in mode 2 while the full
         // pass still finds violators: there the set is about to change and a
         // subproblem solved to mode 1's accuracy picks the same violator, so the
@@ -1094,6 +1095,7 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
                 full_pass<false, false>(a, sh, xo, s, 0, lam, lf, inv_lf, F, kk, vidx);
                 fl += f8n * (unsigned long long)(s + a.l);
             }
+            kfin = kk;
             if (F <= fbest) {
                 fbest = F;
                 if (lane < s) {
@@ -1116,7 +1118,7 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
             if (s >= kMaxSupp) {
                 // the working set is full and the point is not solved: a wider pass
                 // (a later launch) takes the pixel from its best point so far
-                if (a.overflow && kk > (double)a.tol && lane == 0)
+                if (kTier < 2 && a.overflow && kk > (double)a.tol && lane == 0)
                     a.overflow[atomicAdd(a.overflow_count, 1u)] = (int32_t)p;
                 break;
             }
@@ -1183,6 +1185,9 @@ __device__ __forceinline__ void polish_stack(const PolishArgsDev &a)
                 break;
             }
         }
+        // the 32-slot pass hands what it leaves above tol to the FP64 continuation
+        if (kTier == 2 && a.overflow && kfin > (double)a.tol && lane == 0)
+            a.overflow[atomicAdd(a.overflow_count, 1u)] = (int32_t)p;
         // write the best point (complex64) unless it is the starting one
         if (sh.sb >= 0) {
             const int sb = sh.sb;

@@ -33,6 +33,7 @@ def test_options_default(L):
     o = L.l1ls_options_default()
     assert (o.max_iter, round(o.tol, 8), o.c_alpha, o.precision) == (500, 1e-4, 0.5, 0)
     assert o.backtracking == 1 and o.monotone == 1 and o.fp64_polish == 1 and o.warm_start == 0
+    assert o.fp64_continue == 0
 
 
 def _ws(L, n, l, p, o=None):
@@ -71,7 +72,8 @@ def test_argument_errors_before_any_launch(L):
     assert _solve(L, wsb=16) == -3             # workspace too small
     assert _solve(L, stride=-1) == -1
     for field, val in [("tol", 0.0), ("tol", float("nan")), ("c_alpha", 1.0), ("c_alpha", 0.0),
-                       ("max_iter", -1), ("precision", 7), ("warm_start", 2), ("fp64_polish", 3)]:
+                       ("max_iter", -1), ("precision", 7), ("warm_start", 2), ("fp64_polish", 3),
+                       ("fp64_continue", 2)]:
         o = L.l1ls_options_default()
         setattr(o, field, val)
         assert _solve(L, o=o) == -1, field

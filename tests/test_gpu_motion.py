@@ -9,9 +9,11 @@ does real work here.  Checks, as for the scene: the first iterations follow the
 oracle's trajectory; the returned x is judged by its unique parts (the
 certified KKT residual, device vs oracle, and the objective against the
 minimiser's).  A pixel whose minimiser has more than 32 nonzeros is out of the
-FP64 stage's reach and stays unsolved (the FP32 iteration alone stalls above
-tol on this grid): about 17% of the pixels at L = 512 and 4% at L = 1024, so the
-solved-fraction floors below are set under those shares.
+refinement's reach and, by default, stays unsolved (the FP32 iteration alone
+stalls above tol on this grid): about 17% of the pixels at L = 512 and 4% at
+L = 1024, so the solved-fraction floors of the default runs are set under those
+shares.  With fp64_continue such pixels continue Algorithm 1 in FP64, and the
+floor is the oracle's own Algorithm 1 on the same pixels.
 """
 import numpy as np
 import pytest
@@ -110,3 +112,31 @@ def test_motion_full_size(dev, orc):
     p = B32.shape[0]
     idx = np.arange(13, p, p // 128)
     _check(orc, A32, B32, l32, X, d, idx, 1e-4, min_solved=0.8)
+
+
+@pytest.mark.parametrize("cfg", [6, 7])
+def test_motion_fp64_continue(dev, orc, cfg):
+    """fp64_continue: the pixels the 32-slot refinement leaves above tol continue
+    Algorithm 1 in FP64 from its best point (max_iter iterations in all).  The
+    solved fraction reaches the oracle's Algorithm 1 (FP64, same max_iter, from
+    x = 0) on the same pixels, and every certified pixel is the minimiser's."""
+    p = 600 if cfg == 6 else 240
+    A32, B32, l32 = _stack(cfg, p)
+    Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
+    print(f"motion cfg {cfg} p {p} fp64_continue", flush=True)
+    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, fp64_polish=1, polish_after=bench.POLISH_AFTER,
+                     fp64_continue=True)
+    _, d0 = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, fp64_polish=1, polish_after=bench.POLISH_AFTER)
+    A64 = A32.astype(np.complex128)
+    _, do = orc.rbpg_batch(A64, B32.astype(np.complex128), l32.astype(np.float64), tol=1e-4, max_iter=500)
+    oracle_solved = float(np.mean(do["converged"]))
+    conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
+    conv0 = (d0["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
+    print(f"  solved {conv.mean():.4f} (without continuation {conv0.mean():.4f}, oracle's Algorithm 1 "
+          f"{oracle_solved:.4f})")
+    assert conv.mean() >= oracle_solved - 0.01
+    assert conv.mean() > conv0.mean()
+    # pixels solved without the continuation are untouched by it
+    assert (d["kkt"].cpu().numpy()[conv0] == d0["kkt"].cpu().numpy()[conv0]).all()
+    idx = np.arange(0, p, 4 if cfg == 6 else 2)
+    _check(orc, A32, B32, l32, X, d, idx, 1e-4, min_solved=oracle_solved - 0.01)
