@@ -481,8 +481,9 @@ def main():
                     help="pixels of the parity report (-1: the workload's default, 0: none)")
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp64-continue", action="store_true",
-                    help="pixels the 32-slot refinement leaves above tol continue Algorithm 1 in FP64")
+    ap.add_argument("--no-fp64-continue", dest="fp64_continue", action="store_false",
+                    help="return the pixels the 32-slot refinement leaves above tol unsolved instead of "
+                         "continuing Algorithm 1 in FP64")
     ap.add_argument("--alg1-pixels", type=int, default=1 << 20,
                     help="pixels of the Algorithm-1-only leg (0: skip it)")
     ap.add_argument("--copy-probe", action="store_true",

@@ -97,8 +97,8 @@ typedef struct {
                               nonzeros than the 32-slot working set holds, or the active-set
                               walk stalls) continues Algorithm 1 in FP64 from the best point
                               found, until KKT <= tol or max_iter iterations in all (FP32 and
-                              FP64 counted together); needs fp64_polish.  0 (default): such a
-                              pixel is returned unsolved                                    */
+                              FP64 counted together); needs fp64_polish.  Default 1; 0: such a
+                              pixel is returned unsolved                                     */
 } l1ls_options;
 
 /* Device arrays of length P; any may be NULL.

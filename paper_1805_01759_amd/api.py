@@ -24,7 +24,7 @@ def _stream(stream=None):
 
 def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracking=True,
             monotone=True, fp64_polish=1, polish_after=0, warm_start=False,
-            fp64_continue=False) -> _lib.Options:
+            fp64_continue=True) -> _lib.Options:
     o = _lib.load().l1ls_options_default()
     o.max_iter = int(max_iter)
     o.tol = float(tol)

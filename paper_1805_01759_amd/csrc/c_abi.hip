@@ -352,7 +352,7 @@ l1ls_options l1ls_options_default(void)
     o.fp64_polish = 1;
     o.polish_after = 0;
     o.warm_start = 0;
-    o.fp64_continue = 0;
+    o.fp64_continue = 1;
     return o;
 }
 

@@ -33,7 +33,7 @@ def test_options_default(L):
     o = L.l1ls_options_default()
     assert (o.max_iter, round(o.tol, 8), o.c_alpha, o.precision) == (500, 1e-4, 0.5, 0)
     assert o.backtracking == 1 and o.monotone == 1 and o.fp64_polish == 1 and o.warm_start == 0
-    assert o.fp64_continue == 0
+    assert o.fp64_continue == 1
 
 
 def _ws(L, n, l, p, o=None):

@@ -12,8 +12,9 @@ minimiser's).  A pixel whose minimiser has more than 32 nonzeros is out of the
 refinement's reach and, by default, stays unsolved (the FP32 iteration alone
 stalls above tol on this grid): about 17% of the pixels at L = 512 and 4% at
 L = 1024, so the solved-fraction floors of the default runs are set under those
-shares.  With fp64_continue such pixels continue Algorithm 1 in FP64, and the
-floor is the oracle's own Algorithm 1 on the same pixels.
+shares.  With fp64_continue (the default; the full-size test runs with it) such
+pixels continue Algorithm 1 in FP64, and the floor is the oracle's own Algorithm 1
+on the same pixels, or 0.97 at full size.
 """
 import numpy as np
 import pytest
@@ -89,7 +90,7 @@ def test_motion_solve_matches_minimiser(dev, orc, cfg, prec, bar):
     A32, B32, l32 = _stack(cfg, p)
     Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
     X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, precision=prec, fp64_polish=1,
-                     polish_after=bench.POLISH_AFTER)
+                     polish_after=bench.POLISH_AFTER, fp64_continue=False)
     idx = np.arange(0, p, 5 if cfg == 6 else 3)
     _check(orc, A32, B32, l32, X, d, idx, bar, min_solved=0.75 if cfg == 6 else 0.85)
 
@@ -98,7 +99,7 @@ def test_motion_exact_mode(dev, orc):
     """Every pixel refined in FP64 (mode 2): the certified pixels are the minimiser's."""
     A32, B32, l32 = _stack(6, 250)
     Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A32, B32, l32))
-    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=200, fp64_polish=2)
+    X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=200, fp64_polish=2, fp64_continue=False)
     _check(orc, A32, B32, l32, X, d, np.arange(250), 1e-5, min_solved=0.75)
 
 
@@ -111,7 +112,7 @@ def test_motion_full_size(dev, orc):
     X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, fp64_polish=1, polish_after=bench.POLISH_AFTER)
     p = B32.shape[0]
     idx = np.arange(13, p, p // 128)
-    _check(orc, A32, B32, l32, X, d, idx, 1e-4, min_solved=0.8)
+    _check(orc, A32, B32, l32, X, d, idx, 1e-4, min_solved=0.97)
 
 
 @pytest.mark.parametrize("cfg", [6, 7])
@@ -126,7 +127,8 @@ def test_motion_fp64_continue(dev, orc, cfg):
     print(f"motion cfg {cfg} p {p} fp64_continue", flush=True)
     X, d = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, fp64_polish=1, polish_after=bench.POLISH_AFTER,
                      fp64_continue=True)
-    _, d0 = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, fp64_polish=1, polish_after=bench.POLISH_AFTER)
+    _, d0 = api.solve(Ad, Bd, ld, tol=1e-4, max_iter=500, fp64_polish=1, polish_after=bench.POLISH_AFTER,
+                      fp64_continue=False)
     A64 = A32.astype(np.complex128)
     _, do = orc.rbpg_batch(A64, B32.astype(np.complex128), l32.astype(np.float64), tol=1e-4, max_iter=500)
     oracle_solved = float(np.mean(do["converged"]))

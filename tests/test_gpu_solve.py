@@ -250,7 +250,7 @@ def test_fp64_continue_dense_support(dev, orc):
     lam = np.full(p, 0.2, np.float32)
     Ad, Bd, ld = _to_dev(dev, A, B, lam)
     X, d = api.solve(Ad, Bd, ld, max_iter=500, polish_after=12, fp64_polish=1, fp64_continue=True)
-    _, d0 = api.solve(Ad, Bd, ld, max_iter=500, polish_after=12, fp64_polish=1)
+    _, d0 = api.solve(Ad, Bd, ld, max_iter=500, polish_after=12, fp64_polish=1, fp64_continue=False)
     conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
     conv0 = (d0["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
     A64, B64, L64 = _c128(A, B, lam)
