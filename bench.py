@@ -208,6 +208,7 @@ def bench_batched(args):
         solved += sum(int(((st["diag"]["status"] & 1) != 0).sum().item()) for st in stacks)
     dt = time.perf_counter() - t0
     kinds = plan.describe().count("kernel=mfma")
+    streamed = plan.describe().count("kernel=stream")
     # the plain FP32 solver on the same stacks, one solve call after another
     wsp = api.Workspace()
     o_opts = dict(max_iter=args.max_iter, tol=1e-4, precision="fp32", fp64_polish=args.polish,
@@ -231,6 +232,7 @@ def bench_batched(args):
                       "config": {"workload": f"64 uneven TomoSAR stacks, {total} pixels in total, "
                                              "one HIP graph replay per step",
                                  "pixels": total, "stacks_on_mfma_kernel": kinds,
+                                 "stacks_on_streamed_mfma_kernel": streamed,
                                  "solved_fraction": solved / (total * args.steps),
                                  "polish_after": args.polish_after},
                       "compare": {"form": "plain FP32 solve per stack, eager, no plan",

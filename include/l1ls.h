@@ -57,12 +57,32 @@ typedef enum {
  * L1LS_FP32: FP32 MFMA.  L1LS_SPLIT_BF16: every operand split into hi + lo
  * bfloat16 parts, three MFMA passes (hi*hi + hi*lo + lo*hi) with FP32
  * accumulation.  Everything else (prox, step, reductions) is FP32; the
- * refinement and the final optimality check are FP64.  Shapes outside the MFMA
- * kernels (n > 64 or l > 512) run the wave-per-pixel kernel, whose contractions
- * are plain FP32 vector arithmetic: they, and the block form, take L1LS_FP32
- * only and refuse L1LS_SPLIT_BF16 (L1LS_ERR_UNSUPPORTED_SHAPE, also from
- * l1ls_workspace_size and l1ls_plan_create). */
+ * refinement and the final optimality check are FP64.  Split-BF16 exists in the
+ * register-resident MFMA tile only (n <= 64, l <= 512): larger shapes (the
+ * streamed MFMA tile or the wave-per-pixel kernel), the block form and the
+ * iteration kernels STREAM and WAVE take L1LS_FP32 only and refuse
+ * L1LS_SPLIT_BF16 (L1LS_ERR_UNSUPPORTED_SHAPE, also from l1ls_workspace_size and
+ * l1ls_plan_create). */
 typedef enum { L1LS_FP32 = 0, L1LS_SPLIT_BF16 = 1 } l1ls_precision;
+
+/* The kernel that runs the iterations of Algorithm 1 (l1ls_options.iteration_kernel).
+ *  AUTO    the register-resident MFMA tile for n <= 64 and l <= 512, else the
+ *          streamed MFMA tile (l1ls_plan_create times the candidates instead)
+ *  MFMA    the register-resident MFMA tile (n <= 64, l <= 512)
+ *  WAVE    the wave-per-pixel kernel (plain FP32 vector arithmetic; FP32 only)
+ *  STREAM  the streamed MFMA tile: the same FP32 contractions as the register
+ *          tile, with each 16-pixel tile's iterate (x^k, x^{k-1}, G_k, G_{k-1})
+ *          kept in the workspace (l_pad x 512 bytes a persistent workgroup, at
+ *          most 512 of them); FP32 only, any supported shape
+ * A kernel that does not take the shape or precision is refused with
+ * L1LS_ERR_UNSUPPORTED_SHAPE.  The three agree to FP32 rounding; the register
+ * and streamed tiles give bit-identical results for 384 < l <= 512. */
+typedef enum {
+    L1LS_ITER_AUTO = 0,
+    L1LS_ITER_MFMA = 1,
+    L1LS_ITER_WAVE = 2,
+    L1LS_ITER_STREAM = 3
+} l1ls_iteration_kernel;
 
 /* Per-pixel status bits (diag.status). */
 enum {
@@ -99,6 +119,8 @@ typedef struct {
                               found, until KKT <= tol or max_iter iterations in all (FP32 and
                               FP64 counted together); needs fp64_polish.  Default 1; 0: such a
                               pixel is returned unsolved                                     */
+    int32_t iteration_kernel; /* l1ls_iteration_kernel, default L1LS_ITER_AUTO; the workspace
+                              size depends on it (the streamed tile's state)                  */
 } l1ls_options;
 
 /* Device arrays of length P; any may be NULL.

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("backtracking", ctypes.c_int32),
                 ("monotone", ctypes.c_int32), ("fp64_polish", ctypes.c_int32),
                 ("polish_after", ctypes.c_int32), ("warm_start", ctypes.c_int32),
-                ("fp64_continue", ctypes.c_int32)]
+                ("fp64_continue", ctypes.c_int32),
+                ("iteration_kernel", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):

@@ -22,9 +22,12 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+ITERATION_KERNELS = {"auto": 0, "mfma": 1, "wave": 2, "stream": 3}
+
+
 def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracking=True,
             monotone=True, fp64_polish=1, polish_after=0, warm_start=False,
-            fp64_continue=True) -> _lib.Options:
+            fp64_continue=True, iteration_kernel="auto") -> _lib.Options:
     o = _lib.load().l1ls_options_default()
     o.max_iter = int(max_iter)
     o.tol = float(tol)
@@ -36,6 +39,8 @@ def options(*, max_iter=500, tol=1e-4, c_alpha=0.5, precision="fp32", backtracki
     o.polish_after = int(polish_after)
     o.warm_start = int(bool(warm_start))  # X (out) holds the initial points on entry
     o.fp64_continue = int(bool(fp64_continue))  # FP64 Algorithm 1 after the refinement
+    # the kernel of the iterations: auto, mfma (register tile), wave, stream (streamed MFMA tile)
+    o.iteration_kernel = ITERATION_KERNELS[iteration_kernel]
     return o
 
 

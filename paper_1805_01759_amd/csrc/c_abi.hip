@@ -30,7 +30,7 @@ static l1ls_status fail(l1ls_status st, const char *fmt, ...)
 constexpr int kMaxNSolve = 128;
 constexpr int kMaxLSolve = 1024;
 
-bool mfma_supports(int n, int l) { return n <= 64 && l <= 512; }
+bool mfma_supports(int n, int l) { return mfma_tile_shape(n, l); }
 
 l1ls_status set_error(l1ls_status st, const char *fmt, ...)
 {
@@ -56,7 +56,25 @@ l1ls_status check_options(const l1ls_options *o)
         return fail(L1LS_ERR_INVALID_ARG, "fp64_continue must be 0 or 1");
     if (o->fp64_polish < 0 || o->fp64_polish > 2)
         return fail(L1LS_ERR_INVALID_ARG, "fp64_polish must be 0, 1 or 2");
+    if (o->iteration_kernel < L1LS_ITER_AUTO || o->iteration_kernel > L1LS_ITER_STREAM)
+        return fail(L1LS_ERR_INVALID_ARG, "unknown iteration_kernel %d", o->iteration_kernel);
     return L1LS_OK;
+}
+
+int options_choice(const l1ls_options *opt)
+{
+    switch (opt ? opt->iteration_kernel : L1LS_ITER_AUTO) {
+    case L1LS_ITER_MFMA: return kMfma;
+    case L1LS_ITER_WAVE: return kWave;
+    case L1LS_ITER_STREAM: return kStream;
+    default: return kAuto;
+    }
+}
+
+bool needs_stream_state(int n, int l, const l1ls_options *opt)
+{
+    const int c = options_choice(opt);
+    return c == kStream || (c == kAuto && !mfma_tile_shape(n, l));
 }
 
 static l1ls_status check_shape(int32_t n, int32_t l, int64_t p)
@@ -76,6 +94,11 @@ static l1ls_status check_precision(int32_t n, int32_t l, const l1ls_options *o)
     if (o->precision == L1LS_SPLIT_BF16 && !mfma_supports(n, l))
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "split-BF16 needs n <= 64 and l <= 512 (got n = %d, l = %d)", n,
                     l);
+    if (o->precision == L1LS_SPLIT_BF16 &&
+        (o->iteration_kernel == L1LS_ITER_WAVE || o->iteration_kernel == L1LS_ITER_STREAM))
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "split-BF16 runs on the register-resident MFMA tile only");
+    if (o->iteration_kernel == L1LS_ITER_MFMA && !mfma_supports(n, l))
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the register-resident MFMA tile needs n <= 64, l <= 512");
     return L1LS_OK;
 }
 
@@ -131,7 +154,7 @@ SolveOpts solve_opts(const l1ls_options *opt)
 
 // Checks of one stack's arguments before anything is queued.
 l1ls_status check_stack(int32_t n, int32_t l, int64_t p, const void *A, const void *B, const float *lambda,
-                        int64_t lambda_stride, const void *X, const void *ws, size_t ws_bytes)
+                        int64_t lambda_stride, const void *X, const void *ws, size_t ws_bytes, bool stream)
 {
     l1ls_status st = check_shape(n, l, p);
     if (st != L1LS_OK) return st;
@@ -141,13 +164,13 @@ l1ls_status check_stack(int32_t n, int32_t l, int64_t p, const void *A, const vo
         return fail(L1LS_ERR_INVALID_ARG, "A, B, X must be 8-byte aligned and lambda 4-byte aligned");
     if (!aligned(ws, 256)) return fail(L1LS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (lambda_stride < 0) return fail(L1LS_ERR_INVALID_ARG, "lambda_stride must be >= 0");
-    const size_t need = stack_workspace_layout(n, l, p).total;
+    const size_t need = stack_workspace_bytes(n, l, p, stream);
     if (ws_bytes < need) return fail(L1LS_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     return L1LS_OK;
 }
 
-// The iteration variant of a stack (choice kAuto / kMfma / kWave, `alt` an
-// alternative tiling).
+// The iteration variant of a stack (choice kAuto / kMfma / kWave / kStream, `alt`
+// an alternative tiling).
 l1ls_status stack_variant(int32_t n, int32_t l, const l1ls_options *opt, int choice, int alt, IterVariant *v)
 {
     const l1ls_status st = check_precision(n, l, opt);
@@ -179,7 +202,7 @@ StackDesc stack_desc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l
     d.lambda_stride = lambda_stride;
     d.n = n;
     d.l = l;
-    d.keep_residual = v.family == kVarMfma ? 1 : 0;
+    d.keep_residual = v.family == kVarMfma || v.family == kVarStream ? 1 : 0;
     return d;
 }
 
@@ -253,12 +276,15 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
     st = check_options(opt);
     if (st != L1LS_OK) return st;
     if (p == 0) return L1LS_OK;
-    st = check_stack(n, l, p, A, B, lambda, lambda_stride, X, ws, ws_bytes);
-    if (st != L1LS_OK) return st;
+    if (choice == kAuto) choice = options_choice(opt);
+    IterVariant v{};
     if (choice != kBlocks) {
-        IterVariant v;
         st = stack_variant(n, l, opt, choice, alt, &v);
         if (st != L1LS_OK) return st;
+    }
+    st = check_stack(n, l, p, A, B, lambda, lambda_stride, X, ws, ws_bytes, v.family == kVarStream);
+    if (st != L1LS_OK) return st;
+    if (choice != kBlocks) {
         const StackDesc d = stack_desc(n, l, p, A, B, lambda, lambda_stride, X, diag, ws, v);
         return run_stacks(&d, &v, 1, opt, s);
     }
@@ -353,6 +379,7 @@ l1ls_options l1ls_options_default(void)
     o.polish_after = 0;
     o.warm_start = 0;
     o.fp64_continue = 1;
+    o.iteration_kernel = L1LS_ITER_AUTO;
     return o;
 }
 
@@ -367,7 +394,7 @@ l1ls_status l1ls_workspace_size(int32_t n, int32_t l, int64_t p, const l1ls_opti
         if (st == L1LS_OK) st = check_precision(n, l, opt);
         if (st != L1LS_OK) return st;
     }
-    *bytes = stack_workspace_layout(n, l, p).total;
+    *bytes = stack_workspace_bytes(n, l, p, needs_stream_state(n, l, opt));
     return L1LS_OK;
 }
 
@@ -388,7 +415,7 @@ l1ls_status l1ls_solve_noalloc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *
     if (st != L1LS_OK) return st;
     st = check_options(opt);
     if (st != L1LS_OK) return st;
-    const size_t need = stack_workspace_layout(n, l, p).total;
+    const size_t need = stack_workspace_bytes(n, l, p, needs_stream_state(n, l, opt));
     if (need > (size_t)L1LS_NOALLOC_SCRATCH_BYTES)
         return fail(L1LS_ERR_WORKSPACE,
                     "l1ls_solve_noalloc: n=%d, l=%d, p=%lld needs %zu bytes of scratch, above its "

@@ -314,13 +314,14 @@ bool mfma_supports(int n, int l);
 // wave holds 32 unknowns and a workgroup up to eight waves (two per SIMD), else 64
 // (L <= 256) or 128 unknowns a wave and up to four waves; A is staged in LDS
 // where it fits.  Split-BF16 stages its bf16 planes of A in LDS where they fit,
-// else reads them from L2.  Shapes beyond the MFMA kernels (N > 64 or
-// L > 512), or choice kWave, run the wave-per-pixel kernel.
+// else reads them from L2.  Shapes beyond the register tile (N > 64 or L > 512)
+// run the streamed MFMA tile (FP32); choice kStream runs it for any shape, kWave
+// the wave-per-pixel kernel.
 bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant *v)
 {
     IterVariant r{};
     const int l_pad = lpad_for(l), waves = waves_for(l), T = rows_pad_for(n) / 16;
-    if (choice == kWave || !mfma_supports(n, l)) {
+    if (choice == kWave) {
         if (alt != 0 || precision != L1LS_FP32) return false;
         r.family = kVarWave;
         r.nc = wave_chunks(l);
@@ -328,6 +329,16 @@ bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant 
         r.prec = L1LS_FP32;
         *v = r;
         return r.nc > 0;
+    }
+    if (choice == kStream || !mfma_supports(n, l)) {
+        if (alt != 0 || precision != L1LS_FP32 || T > 8) return false;
+        r.family = kVarStream;
+        r.T = T;
+        r.waves = 4;
+        r.wmax = 4;
+        r.prec = L1LS_FP32;
+        *v = r;
+        return true;
     }
     FistaArgs probe{};
     probe.n = n;
@@ -368,6 +379,7 @@ bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant 
 size_t iter_variant_lds(const IterVariant &v, int n, int l)
 {
     if (v.family == kVarWave) return fista_wave_lds(n, l);
+    if (v.family == kVarStream) return fista_stream_lds_bytes(v.T);
     return fista_mfma_lds_bytes(n, lpad_for(l), v.waves, v.alds != 0, v.prec);
 }
 
@@ -400,6 +412,7 @@ static hipError_t launch_mfma_t(const StackTable &t, const IterVariant &v, hipSt
 hipError_t launch_iteration_table(const StackTable &t, const IterVariant &v, hipStream_t s)
 {
     if (v.family == kVarWave) return launch_wave_table(t, v.nc, s);
+    if (v.family == kVarStream) return launch_stream_table(t, v.T, s);
     const bool bf = v.prec == L1LS_SPLIT_BF16;
     switch (v.T) {
     case 1: return bf ? launch_mfma_t<1, L1LS_SPLIT_BF16>(t, v, s) : launch_mfma_t<1, L1LS_FP32>(t, v, s);

@@ -47,6 +47,7 @@ struct FistaArgs {
                               // [2] refinement FP64 flops, [3] refinement FP32 flops
     int32_t *polish_list;
     float2 *R;                // p x n: residual A x - b of the returned x (FP32), or null
+    float2 *fstate;           // streamed tile: iterate state, stream_tile_bytes(l_pad) per workgroup
     int32_t fista_cap;        // retire unsolved pixels after this many iterations
     float tol, c_alpha;
     int32_t backtracking, monotone, polish;
@@ -132,10 +133,23 @@ __host__ __device__ inline int zblocks_for(int n) { return (2 * n + 15) / 16; }
 __host__ __device__ inline int rows_pad_for(int n) { return 16 * ((n + 15) / 16); }
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) / 256 * 256; }
 
+// The register-resident MFMA tile takes up to 64 rows and 512 bins; larger shapes
+// run the streamed MFMA tile, whose iterate state (x^k, x^{k-1}, G_k, G_{k-1} of
+// 16 pixels: l_pad x 512 bytes a tile) lives in a workspace region, one slot per
+// persistent workgroup (at most kStreamGroups of them).
+__host__ __device__ inline bool mfma_tile_shape(int n, int l) { return n <= 64 && l <= 512; }
+constexpr int kStreamGroups = 512;
+__host__ __device__ inline int64_t stream_groups_for(int64_t p)
+{
+    const int64_t tiles = (p + 15) / 16;
+    return tiles < kStreamGroups ? tiles : kStreamGroups;
+}
+__host__ __device__ inline size_t stream_tile_bytes(int l_pad) { return (size_t)l_pad * 512; }
+
 // Workspace layout for one stack (byte offsets; every region 256-byte aligned).
 struct StackWorkspace {
     size_t a_packed, a_trans, a_bf16, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid,
-        overflow, hgram, cbuf, total;
+        overflow, hgram, cbuf, fstate, total;
 };
 __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
 {
@@ -176,8 +190,18 @@ __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, i
     w.cbuf = off;
     const int64_t groups = p < kMaxRefineGroups ? p : kMaxRefineGroups;
     off = ws_align(off + (size_t)groups * l * sizeof(double2));
+    // the streamed MFMA tile's iterate state comes last, where that kernel runs
+    // the stack (stack_workspace_bytes)
+    w.fstate = off;
     w.total = off;
     return w;
+}
+
+// Bytes of a stack's workspace, with or without the streamed tile's state.
+__host__ __device__ inline size_t stack_workspace_bytes(int n, int l, int64_t p, bool stream)
+{
+    const StackWorkspace w = stack_workspace_layout(n, l, p);
+    return stream ? ws_align(w.fstate + (size_t)stream_groups_for(p) * stream_tile_bytes(lpad_for(l))) : w.total;
 }
 
 // ---------------------------------------------------------------------------
@@ -244,6 +268,7 @@ __host__ __device__ inline FistaArgs fista_args_for(const StackDesc &d, const So
     fa.polish_list = (int32_t *)(d.ws + lay.polish_list);
     fa.work = (unsigned long long *)(d.ws + lay.work);
     fa.R = d.keep_residual ? (float2 *)(d.ws + lay.resid) : nullptr;
+    fa.fstate = (float2 *)(d.ws + lay.fstate);
     fa.fista_cap = o.fista_cap;
     fa.tol = o.tol;
     fa.c_alpha = o.c_alpha;
@@ -330,9 +355,10 @@ hipError_t launch_continue_table(const StackTable &t, hipStream_t s);     // FP6
 
 // The iteration kernel that runs a stack: the split re/im MFMA tile (T row
 // blocks, KB unknown blocks per wave, A staged in LDS or read from L2, up to
-// WMAX waves of which `waves` run), or the wave-per-pixel kernel (NC chunks).
+// WMAX waves of which `waves` run), the streamed MFMA tile (T row blocks, four
+// waves, iterate state in the workspace), or the wave-per-pixel kernel (NC chunks).
 struct IterVariant {
-    int family;   // kVarMfma, kVarWave
+    int family;   // kVarMfma, kVarStream, kVarWave
     int T, KB, alds, prec, wmax, waves, nc;
     bool operator==(const IterVariant &o) const
     {
@@ -340,7 +366,7 @@ struct IterVariant {
                wmax == o.wmax && waves == o.waves && nc == o.nc;
     }
 };
-enum { kVarMfma = 1, kVarWave = 2 };
+enum { kVarMfma = 1, kVarWave = 2, kVarStream = 3 };
 // The default variant for a shape and precision (kMfma: the MFMA families, kWave:
 // the wave kernel); `alt` selects an alternative tiling for the autotuner
 // (0 default, 1 the other A placement, 2 the other unknowns-per-wave split);
@@ -359,7 +385,7 @@ size_t fista_blocks_lds(int n, int l_pad, int J);
 size_t fista_wave_lds(int n, int l);
 
 // Which iteration kernel runs a stack.
-enum KernelChoice { kAuto = 0, kMfma = 1, kWave = 2, kBlocks = 3 };
+enum KernelChoice { kAuto = 0, kMfma = 1, kWave = 2, kBlocks = 3, kStream = 4 };
 bool mfma_supports(int n, int l);
 l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B,
                         const float *lambda, int64_t lambda_stride, const l1ls_options *opt,
@@ -368,7 +394,11 @@ l1ls_status solve_stack(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, cons
                         const double *draws = nullptr, int alt = 0);
 l1ls_status check_options(const l1ls_options *o);
 l1ls_status check_stack(int32_t n, int32_t l, int64_t p, const void *A, const void *B, const float *lambda,
-                        int64_t lambda_stride, const void *X, const void *ws, size_t ws_bytes);
+                        int64_t lambda_stride, const void *X, const void *ws, size_t ws_bytes, bool stream);
+// Whether the options' iteration kernel for this shape is the streamed tile (its
+// state then needs workspace), and the kernel choice the options ask for.
+bool needs_stream_state(int n, int l, const l1ls_options *opt);
+int options_choice(const l1ls_options *opt);
 l1ls_status stack_variant(int32_t n, int32_t l, const l1ls_options *opt, int choice, int alt, IterVariant *v);
 StackDesc stack_desc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const l1ls_c32 *B, const float *lambda,
                      int64_t lambda_stride, l1ls_c32 *X, const l1ls_diag *diag, void *ws, const IterVariant &v);
@@ -385,5 +415,7 @@ hipError_t launch_unrolled_backward(int n, int l, int64_t p, const float2 *B, fl
                                     const float2 *dX, float2 *dB, float *dlambda, float *dxi,
                                     void *ws, hipStream_t st);
 size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precision);
+size_t fista_stream_lds_bytes(int T);
+hipError_t launch_stream_table(const StackTable &t, int T, hipStream_t s);
 
 }  // namespace l1ls

@@ -1,6 +1,7 @@
 // Batched stacks of uneven shape: a plan assigns each stack an iteration tiling
 // (register-resident MFMA tiles with A in LDS or from L2 and 32 or 64 unknowns
-// a wave, or the wave-per-pixel form), chosen by an autotuner that times the
+// a wave, the streamed MFMA tile, or the wave-per-pixel form), chosen by an
+// autotuner (or named by the options' iteration_kernel) that times the
 // candidates on a synthetic stack of the same (N, L) and keeps the result on
 // disk, and lays out one workspace slice per stack.  Execution queues the
 // solve of all stacks as stack tables: one setup launch, one persistent
@@ -46,8 +47,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // Autotuner: per (device, n, l, precision, refinement mode) the fastest of the
 // iteration tilings that exist for the shape (the MFMA tile with A in LDS or
-// from L2, 32 or 64 unknowns a wave for short stacks, or the wave-per-pixel
-// kernel), timed on a synthetic stack of that shape.  Results are kept for the
+// from L2, 32 or 64 unknowns a wave for short stacks; beyond it the streamed
+// tile; and the wave-per-pixel kernel), timed on a synthetic stack of that shape.  Results are kept for the
 // process and in a text cache file (one "device n l precision mode family T KB
 // alds waves nc" line per shape): $L1LS_TUNE_CACHE, else
 // $XDG_CACHE_HOME/l1ls/tune.txt, else $HOME/.cache/l1ls/tune.txt; "off" disables it.
@@ -99,7 +100,7 @@ void tune_load_locked()
         l1ls_options o{};
         o.precision = prec;
         o.fp64_polish = mode;
-        v.prec = v.family == kVarWave ? L1LS_FP32 : prec;
+        v.prec = v.family == kVarMfma ? prec : L1LS_FP32;
         v.wmax = v.family == kVarMfma && v.KB == 2 ? 8 : 4;
         g_tune_cache[tune_key(dev, n, l, o)] = v;
     }
@@ -161,6 +162,9 @@ IterVariant autotune(int n, int l, const l1ls_options &opt, int dev)
     for (int alt = 0; alt < 3; ++alt)
         if (mfma_supports(n, l) && iter_variant(n, l, opt.precision, kMfma, alt, &probe))
             cands.push_back({kMfma, alt});
+    // beyond the register tile: the streamed tile (FP32, as the wave kernel)
+    if (!mfma_supports(n, l) && opt.precision == L1LS_FP32 && iter_variant(n, l, opt.precision, kStream, 0, &probe))
+        cands.push_back({kStream, 0});
     if (opt.precision == L1LS_FP32) cands.push_back({kWave, 0});  // the wave kernel is FP32 only
     IterVariant best_v;
     iter_variant(n, l, opt.precision, cands[0].first, cands[0].second, &best_v);
@@ -194,7 +198,7 @@ IterVariant autotune(int n, int l, const l1ls_options &opt, int dev)
         }
         l1ls_options o = opt;
         o.warm_start = 0;
-        const size_t wsb = stack_workspace_layout(n, l, p).total;
+        const size_t wsb = stack_workspace_bytes(n, l, p, true);
         void *dA = nullptr, *dB = nullptr, *dl = nullptr, *dX = nullptr, *dws = nullptr;
         if (hipMalloc(&dA, hA.size() * 4) == hipSuccess && hipMalloc(&dB, hB.size() * 4) == hipSuccess &&
             hipMalloc(&dl, hl.size() * 4) == hipSuccess && hipMalloc(&dX, (size_t)p * l * 8) == hipSuccess &&
@@ -252,12 +256,15 @@ l1ls_status l1ls_plan_create(const l1ls_stack *stacks, int32_t count, const l1ls
         it.n = stacks[i].n;
         it.l = stacks[i].l;
         it.p = stacks[i].p;
-        if (it.p > 0) {
+        if (opt->iteration_kernel != L1LS_ITER_AUTO) {
+            // the kernel the options name (l1ls_workspace_size has checked that it takes the shape)
+            iter_variant(it.n, it.l, opt->precision, options_choice(opt), 0, &it.var);
+        } else if (it.p > 0) {
             it.var = autotune(it.n, it.l, *opt, pl->device);
         } else {
             iter_variant(it.n, it.l, opt->precision, kAuto, 0, &it.var);
         }
-        l1ls_workspace_size(it.n, it.l, it.p, opt, &it.ws_bytes);
+        it.ws_bytes = stack_workspace_bytes(it.n, it.l, it.p, it.var.family == kVarStream);
         it.ws_off = off;
         off += (it.ws_bytes + 255) / 256 * 256;
         it.cost = (double)it.p * it.n * it.l;
@@ -303,7 +310,7 @@ l1ls_status l1ls_plan_execute(l1ls_plan *plan, const l1ls_stack *stacks, void *w
         const l1ls_stack &sk = stacks[idx];
         char *ws = (char *)workspace + it.ws_off;
         const l1ls_status st = check_stack(it.n, it.l, it.p, sk.A, sk.B, sk.lambda, sk.lambda_stride, sk.X, ws,
-                                           it.ws_bytes);
+                                           it.ws_bytes, it.var.family == kVarStream);
         if (st != L1LS_OK) return st;
         descs.push_back(stack_desc(it.n, it.l, it.p, sk.A, sk.B, sk.lambda, sk.lambda_stride, sk.X, &sk.diag, ws,
                                    it.var));
@@ -326,6 +333,9 @@ int32_t l1ls_plan_describe(const l1ls_plan *plan, char *buf, int32_t buf_len)
         if (v.family == kVarWave)
             snprintf(line, sizeof line, "stack %zu: n=%d l=%d p=%lld kernel=wave chunks=%d\n", i, it.n, it.l,
                      (long long)it.p, v.nc);
+        else if (v.family == kVarStream)
+            snprintf(line, sizeof line, "stack %zu: n=%d l=%d p=%lld kernel=stream T=%d waves=%d\n", i, it.n,
+                     it.l, (long long)it.p, v.T, v.waves);
         else
             snprintf(line, sizeof line, "stack %zu: n=%d l=%d p=%lld kernel=%s T=%d KB=%d waves=%d A=%s\n", i, it.n,
                      it.l, (long long)it.p, "mfma", v.T, v.KB, v.waves,

@@ -126,3 +126,34 @@ def test_split_bf16_refused_without_an_mfma_kernel(L):
                              ctypes.byref(o), 2, ctypes.c_void_p(512), ctypes.c_void_p(128), None,
                              ctypes.c_void_p(256), 1 << 20, None)
     assert st == -2 and b"FP32 only" in L.l1ls_last_error()
+
+
+def test_iteration_kernel_option(L):
+    # the streamed MFMA tile keeps each persistent workgroup's iterate in the workspace:
+    # l_pad x 512 bytes for each of min(tiles of 16 pixels, 512) workgroups
+    o = L.l1ls_options_default()
+    assert o.iteration_kernel == 0
+    st, auto_big = _ws(L, 100, 1024, 1 << 16, o)
+    o.iteration_kernel = 2  # the wave kernel keeps no such state
+    st2, wave_big = _ws(L, 100, 1024, 1 << 16, o)
+    assert st == 0 and st2 == 0 and auto_big - wave_big == 512 * 1024 * 512
+    o.iteration_kernel = 3  # streamed tile on a register-tile shape: 7 tiles of 16 pixels
+    _, s_small = _ws(L, 50, 512, 100, o)
+    o.iteration_kernel = 0
+    _, a_small = _ws(L, 50, 512, 100, o)
+    assert s_small - a_small == 7 * 512 * 512
+    o.iteration_kernel = 1  # the register tile takes n <= 64, l <= 512 only
+    assert _ws(L, 65, 256, 1, o)[0] == -2
+    assert _solve(L, n=50, l=600, o=o, wsb=1 << 26) == -2
+    assert _ws(L, 64, 512, 1, o)[0] == 0
+    o.iteration_kernel = 4
+    assert _ws(L, 10, 10, 1, o)[0] == -1
+    assert _solve(L, o=o) == -1
+    o.precision = 1  # split-BF16 only on the register tile
+    for k in (2, 3):
+        o.iteration_kernel = k
+        assert _ws(L, 50, 512, 1, o)[0] == -2
+        assert b"split-BF16" in L.l1ls_last_error()
+    o.precision = 0
+    o.iteration_kernel = 3
+    assert _solve(L, o=o, wsb=16) == -3  # workspace checked against the streamed tile's size

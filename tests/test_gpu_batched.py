@@ -1,5 +1,6 @@
-"""Batched uneven stacks (plan + HIP graph) and the wave-per-pixel kernel for
-shapes beyond the register-resident MFMA tiles, against the FP64 oracle."""
+"""Batched uneven stacks (plan + HIP graph), and the streamed MFMA tile and the
+wave-per-pixel kernel for shapes beyond the register-resident MFMA tiles, against
+the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -21,12 +22,13 @@ def _stack(ss):
     return synth.to_device_dtypes(geom.A, B, lam)
 
 
+@pytest.mark.parametrize("kernel", ["auto", "wave"])
 @pytest.mark.parametrize("n,l,p", [(100, 1024, 24), (80, 300, 40), (128, 64, 20), (11, 700, 33)])
-def test_large_shapes(dev, orc, n, l, p):
+def test_large_shapes(dev, orc, n, l, p, kernel):
     ss = synth.StackSpec(90 + n % 7, n, l, p)
     A, B, lam = _stack(ss)
     Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A, B, lam))
-    X, d = api.solve(Ad, Bd, ld, fp64_polish=2, polish_after=100)
+    X, d = api.solve(Ad, Bd, ld, fp64_polish=2, polish_after=100, iteration_kernel=kernel)
     A64, B64, L64 = A.astype(complex), B.astype(complex), lam.astype(float)
     Xe, de = orc.exact_batch(A64, B64, L64)
     Xg = X.cpu().numpy().astype(complex)
@@ -139,8 +141,8 @@ def test_plan_tuning_cache_file(dev, tmp_path):
     for ln, (n, l) in zip(lines, [(20, 200), (40, 500), (90, 700)]):
         f = ln.split()
         assert len(f) == 11 and (int(f[1]), int(f[2])) == (n, l) and f[4] == "1"
-        assert f[5] in ("1", "2")
-    assert lines[2].split()[5] == "2"  # n = 90 > 64: only the wave kernel exists
+        assert f[5] in ("1", "2", "3")
+    assert lines[2].split()[5] in ("2", "3")  # n = 90 > 64: the streamed tile or the wave kernel
     r2 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
     assert r2.returncode == 0, r2.stderr
     assert r2.stdout == r1.stdout
