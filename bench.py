@@ -53,6 +53,7 @@ KERNEL_SOURCES = {
     "fista_mfma_kernel": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
     "fista_mfma_kernel_bf16": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
     "fista_wave_kernel": ("fista_wave.hip", "l1ls_internal.h"),
+    "fista_stream_kernel": ("fista_stream.hip", "fista_mfma.h", "l1ls_internal.h"),
     "polish_kernel": ("polish.hip", "wave_reduce.h", "l1ls_internal.h"),
     "certify_kernel": ("certify.hip", "wave_reduce.h", "l1ls_internal.h"),
 }
@@ -434,7 +435,8 @@ def rooflines(r, n, l, prec, workload, polish):
         else:
             it_kernel = "fista_mfma_kernel_bf16"
     else:
-        it_kernel = "fista_wave_kernel"
+        # beyond the register tile the default is the streamed MFMA tile (FP32)
+        it_kernel = "fista_stream_kernel"
     # iteration kernel: algorithmic flops = (forward + adjoint products) x 8 N L
     it_flops = (r["fwd"] + r["adj"]) * 8.0 * n * l
     it_ach = it_flops / avg_s["iteration"]

@@ -539,7 +539,8 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
 // stream_groups_for(p) slots: the workgroups beyond that (more than the stack
 // has tiles) leave the stack to the others.
 template <int T>
-__global__ void __launch_bounds__(64 * kStreamWaves) fista_stream_kernel(const StackTable t)
+__global__ void __launch_bounds__(64 * kStreamWaves) __attribute__((amdgpu_waves_per_eu(T <= 4 ? 2 : 1)))
+fista_stream_kernel(const StackTable t)
 {
     for (int i = 0; i < t.count; ++i) {
         if (t.d[i].p <= 0) continue;
