@@ -370,7 +370,8 @@ def run_precision(api, Ad, Bd, ld, X, ws, n, l, p, prec, steps, warmup, args, sa
     the last solve (x and the CONVERGED bit) for the parity report."""
     import torch
     opts = dict(max_iter=args.max_iter, tol=1e-4, precision=prec, fp64_polish=args.polish,
-                polish_after=args.polish_after, fp64_continue=args.fp64_continue)
+                polish_after=args.polish_after, fp64_continue=args.fp64_continue,
+                iteration_kernel=args.iteration_kernel if prec == "fp32" else "auto")
     for _ in range(warmup):
         api.solve(Ad, Bd, ld, out=X, workspace=ws, **opts)
     torch.cuda.synchronize()
@@ -426,10 +427,12 @@ def algorithm1_only(api, Ad, Bd, ld, X, n, l, args):
             "note": "Algorithm 1 in FP32 on the MFMA kernel, no FP64 refinement; FP64 certificate"}
 
 
-def rooflines(r, n, l, prec, workload, polish):
+def rooflines(r, n, l, prec, workload, polish, kernel="auto"):
     """Roofline objects of the iteration and refinement kernels of one run."""
     avg_s = r["avg_s"]
-    if n <= 64 and l <= 512:
+    if prec == "fp32" and kernel in ("stream", "wave"):
+        it_kernel = f"fista_{kernel}_kernel"
+    elif n <= 64 and l <= 512:
         if prec == "fp32":
             it_kernel = "fista_mfma_kernel"
         else:
@@ -485,6 +488,9 @@ def main():
                     help="pixels of the parity report (-1: the workload's default, 0: none)")
     ap.add_argument("--pixels", type=int, default=0, help="override the pixel count (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iteration-kernel", default="auto", choices=["auto", "mfma", "wave", "stream"],
+                    help="kernel of the FP32 iterations (auto: the register tile where it exists, "
+                         "else the streamed tile)")
     ap.add_argument("--no-fp64-continue", dest="fp64_continue", action="store_false",
                     help="return the pixels the 32-slot refinement leaves above tol unsolved instead of "
                          "continuing Algorithm 1 in FP64")
@@ -554,7 +560,7 @@ def main():
                                     max(1, min(args.steps, args.compare_steps)),
                                     min(args.warmup, 1), args, sample_idx)
     r = runs[args.precision]
-    roof_it, roof_rf = rooflines(r, n, l, args.precision, args.workload, args.polish)
+    roof_it, roof_rf = rooflines(r, n, l, args.precision, args.workload, args.polish, args.iteration_kernel)
     # the dominant kernel by event-timed duration
     roof = roof_rf if roof_rf is not None and r["avg_s"]["refine"] > r["avg_s"]["iteration"] else roof_it
     rec = {
@@ -574,6 +580,7 @@ def main():
                    "pixels": p, "max_iter": args.max_iter, "tol": 1e-4, "precision": args.precision,
                    "polish_after": args.polish_after, "fp64_polish": args.polish,
                    "fp64_continue": int(args.fp64_continue),
+                   "iteration_kernel": args.iteration_kernel,
                    "solved_fraction": r["solved_fraction"], "pixels_refined_fp64": r["npol"],
                    "kernel_ms": {kc: v * 1e3 for kc, v in r["avg_s"].items()}},
         "roofline": roof,

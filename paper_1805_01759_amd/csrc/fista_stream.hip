@@ -158,15 +158,19 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
         return S;
     };
 
-    // W += A d for one block of complex d (the register tile's order of products)
-    auto fwd_block = [&](int b, const float (&dr)[4], const float (&di)[4], f4 (&Wr)[T], f4 (&Wi)[T]) {
+    // A operands of block b for the forward product (issued ahead of the element
+    // work that forms d, so that their L2 latency hides under it)
+    auto fwd_load = [&](int b, f4 (&a01)[T], f4 (&a23)[T]) {
         const int m0 = 16 * b + 4 * h;
-        f4 a01[T], a23[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            a01[t] = Av.load4(16 * t + j, m0);
-            a23[t] = Av.load4(16 * t + j, m0 + 2);
+            a01[t] = Av.load4(16 * t + j, m0);      // (re, im) of m0, m0 + 1
+            a23[t] = Av.load4(16 * t + j, m0 + 2);  // (re, im) of m0 + 2, m0 + 3
         }
+    };
+    // W += A d for one block of complex d (the register tile's order of products)
+    auto fwd_mfma = [&](const f4 (&a01)[T], const f4 (&a23)[T], const float (&dr)[4], const float (&di)[4],
+                        f4 (&Wr)[T], f4 (&Wi)[T]) {
         float ndi[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) ndi[q] = -di[q];
@@ -275,7 +279,9 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
                 fs::st_blk(fs::blk(st, NB, 3, b, lane), zero, zero);
             }
             // W_re += A_re x_re - A_im x_im;  W_im += A_im x_re + A_re x_im
-            fwd_block(b, xr, xi, Vr, Vi);
+            f4 a01[T], a23[T];
+            fwd_load(b, a01, a23);
+            fwd_mfma(a01, a23, xr, xi, Vr, Vi);
         }
         l1p = fm::sum_h(l1p);
         const f4 S = reduce(Vr, Vi, f4{l1p, 0.0f, 0.0f, 0.0f});
@@ -297,21 +303,30 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
     };
 
     // ---- G_k = 2 A^H r_k for the wave's blocks (all slots), into the pair's `sel` array
+    // (a block's A operands are all issued before its products)
+    auto adj_load = [&](int b, float2 (&av)[T][4]) {
+        const int m = 16 * b + j;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) av[t][q] = Av.load2(16 * t + 4 * h + q, m);
+    };
     auto adjoint = [&]() {
         for (int b = b_lo; b < b_hi; ++b) {
+            float2 av[T][4];
+            adj_load(b, av);
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
             f4 gr = f4{0.0f, 0.0f, 0.0f, 0.0f}, gi = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            const int m = 16 * b + j;
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float2 av = Av.load2(16 * t + 4 * h + q, m);
                     // G_re += A_re (2 r_re) + A_im (2 r_im);  G_im += A_re (2 r_im) - A_im (2 r_re)
                     const float pr = 2.0f * Rr[t][q], pi = 2.0f * Ri[t][q], npr = -2.0f * Rr[t][q];
-                    gr = fm::mfma(av.x, pr, gr);
-                    gr = fm::mfma(av.y, pi, gr);
-                    gi = fm::mfma(av.x, pi, gi);
-                    gi = fm::mfma(av.y, npr, gi);
+                    gr = fm::mfma(av[t][q].x, pr, gr);
+                    gr = fm::mfma(av[t][q].y, pi, gr);
+                    gi = fm::mfma(av[t][q].x, pi, gi);
+                    gi = fm::mfma(av[t][q].y, npr, gi);
                 }
             const float g_r[4] = {gr[0], gr[1], gr[2], gr[3]}, g_i[4] = {gi[0], gi[1], gi[2], gi[3]};
             fs::st_blk(fs::blk(st, NB, 2 + sel, b, lane), g_r, g_i);
@@ -338,6 +353,8 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
             for (int t = 0; t < T; ++t) Wr[t] = Wi[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
             float d2 = 0.0f, s1 = 0.0f, kmax = 0.0f;
             for (int b = b_lo; b < b_hi; ++b) {
+                f4 a01[T], a23[T];
+                fwd_load(b, a01, a23);
                 float x_r[4], x_i[4], xp_r[4], xp_i[4], g_r[4], g_i[4], gp_r[4], gp_i[4];
                 fs::ld_blk(fs::blk(st, NB, xs, b, lane), x_r, x_i);
                 fs::ld_blk(fs::blk(st, NB, xps, b, lane), xp_r, xp_i);
@@ -367,7 +384,7 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
                     d2 = fmaf(dr[q], dr[q], fmaf(di[q], di[q], d2));
                     s1 += axb - __builtin_amdgcn_sqrtf(fmaf(x_r[q], x_r[q], x_i[q] * x_i[q]));
                 }
-                fwd_block(b, dr, di, Wr, Wi);
+                fwd_mfma(a01, a23, dr, di, Wr, Wi);
             }
             d2 = fm::sum_h(d2);
             s1 = fm::sum_h(s1);
