@@ -430,15 +430,14 @@ def algorithm1_only(api, Ad, Bd, ld, X, n, l, args):
 def rooflines(r, n, l, prec, workload, polish, kernel="auto"):
     """Roofline objects of the iteration and refinement kernels of one run."""
     avg_s = r["avg_s"]
-    if prec == "fp32" and kernel in ("stream", "wave"):
+    if prec != "fp32":
+        it_kernel = "fista_mfma_kernel_bf16"
+    elif kernel != "auto":
         it_kernel = f"fista_{kernel}_kernel"
-    elif n <= 64 and l <= 512:
-        if prec == "fp32":
-            it_kernel = "fista_mfma_kernel"
-        else:
-            it_kernel = "fista_mfma_kernel_bf16"
+    elif n <= 64 and l <= 384:
+        it_kernel = "fista_mfma_kernel"
     else:
-        # beyond the register tile the default is the streamed MFMA tile (FP32)
+        # the automatic FP32 choice beyond 384 bins: the streamed MFMA tile
         it_kernel = "fista_stream_kernel"
     # iteration kernel: algorithmic flops = (forward + adjoint products) x 8 N L
     it_flops = (r["fwd"] + r["adj"]) * 8.0 * n * l

@@ -66,8 +66,11 @@ typedef enum {
 typedef enum { L1LS_FP32 = 0, L1LS_SPLIT_BF16 = 1 } l1ls_precision;
 
 /* The kernel that runs the iterations of Algorithm 1 (l1ls_options.iteration_kernel).
- *  AUTO    the register-resident MFMA tile for n <= 64 and l <= 512, else the
- *          streamed MFMA tile (l1ls_plan_create times the candidates instead)
+ *  AUTO    in FP32 the streamed MFMA tile, except for n <= 64 and l <= 384,
+ *          which run the register-resident tile (as split-BF16 does for every
+ *          n <= 64, l <= 512); l1ls_plan_create times the candidates instead, and
+ *          l1ls_solve_noalloc takes the register tile where the streamed tile's
+ *          state would not fit its scratch
  *  MFMA    the register-resident MFMA tile (n <= 64, l <= 512)
  *  WAVE    the wave-per-pixel kernel (plain FP32 vector arithmetic; FP32 only)
  *  STREAM  the streamed MFMA tile: the same FP32 contractions as the register
@@ -173,8 +176,9 @@ l1ls_status l1ls_solve(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A, const
  * is created.  The stream must belong to the current device.
  *  - returns L1LS_ERR_WORKSPACE, with no work queued, when l1ls_workspace_size
  *    for (n, l, p) exceeds L1LS_NOALLOC_SCRATCH_BYTES (e.g. n = 25, l = 256
- *    holds about 220,000 pixels, n = 50, l = 512 about 68,000); split the
- *    pixels or call l1ls_solve.
+ *    holds about 220,000 pixels, n = 50, l = 512 about 68,000 on the register
+ *    tile, which the automatic kernel choice takes here when the streamed
+ *    tile's state would not fit); split the pixels or call l1ls_solve.
  *  - every call on one device shares that device's array, which keeps the last
  *    call's contents (the kernels clear what must start at zero): calls that
  *    overlap in time on one device race and give undefined results; serialise

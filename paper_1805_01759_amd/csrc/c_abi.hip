@@ -74,7 +74,7 @@ int options_choice(const l1ls_options *opt)
 bool needs_stream_state(int n, int l, const l1ls_options *opt)
 {
     const int c = options_choice(opt);
-    return c == kStream || (c == kAuto && !mfma_tile_shape(n, l));
+    return c == kStream || (c == kAuto && auto_stream(n, l, opt ? opt->precision : L1LS_FP32));
 }
 
 static l1ls_status check_shape(int32_t n, int32_t l, int64_t p)
@@ -415,7 +415,16 @@ l1ls_status l1ls_solve_noalloc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *
     if (st != L1LS_OK) return st;
     st = check_options(opt);
     if (st != L1LS_OK) return st;
-    const size_t need = stack_workspace_bytes(n, l, p, needs_stream_state(n, l, opt));
+    bool state = needs_stream_state(n, l, opt);
+    int choice = options_choice(opt);
+    if (state && choice == kAuto && mfma_supports(n, l) &&
+        stack_workspace_bytes(n, l, p, true) > (size_t)L1LS_NOALLOC_SCRATCH_BYTES) {
+        // the automatic choice takes the register tile when the streamed tile's
+        // state does not fit the scratch (the same results bit for bit)
+        state = false;
+        choice = kMfma;
+    }
+    const size_t need = stack_workspace_bytes(n, l, p, state);
     if (need > (size_t)L1LS_NOALLOC_SCRATCH_BYTES)
         return fail(L1LS_ERR_WORKSPACE,
                     "l1ls_solve_noalloc: n=%d, l=%d, p=%lld needs %zu bytes of scratch, above its "
@@ -427,7 +436,7 @@ l1ls_status l1ls_solve_noalloc(int32_t n, int32_t l, int64_t p, const l1ls_c32 *
     if (st != L1LS_OK) return st;
     g_no_events = true;
     st = solve_stack(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, ws,
-                     (size_t)L1LS_NOALLOC_SCRATCH_BYTES, stream, kAuto);
+                     (size_t)L1LS_NOALLOC_SCRATCH_BYTES, stream, choice);
     g_no_events = false;
     return st;
 }

@@ -315,8 +315,9 @@ bool mfma_supports(int n, int l);
 // (L <= 256) or 128 unknowns a wave and up to four waves; A is staged in LDS
 // where it fits.  Split-BF16 stages its bf16 planes of A in LDS where they fit,
 // else reads them from L2.  Shapes beyond the register tile (N > 64 or L > 512)
-// run the streamed MFMA tile (FP32); choice kStream runs it for any shape, kWave
-// the wave-per-pixel kernel.
+// run the streamed MFMA tile (FP32), and so does kAuto in FP32 for 384 < L <= 512
+// (auto_stream); choice kStream runs it for any shape, kWave the wave-per-pixel
+// kernel, kMfma the register tile.
 bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant *v)
 {
     IterVariant r{};
@@ -330,7 +331,7 @@ bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant 
         *v = r;
         return r.nc > 0;
     }
-    if (choice == kStream || !mfma_supports(n, l)) {
+    if (choice == kStream || (choice == kAuto && auto_stream(n, l, precision)) || !mfma_supports(n, l)) {
         if (alt != 0 || precision != L1LS_FP32 || T > 8) return false;
         r.family = kVarStream;
         r.T = T;

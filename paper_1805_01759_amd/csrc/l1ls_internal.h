@@ -139,6 +139,13 @@ __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) / 256 * 
 // persistent workgroup (at most kStreamGroups of them).
 __host__ __device__ inline bool mfma_tile_shape(int n, int l) { return n <= 64 && l <= 512; }
 constexpr int kStreamGroups = 512;
+// The automatic choice: the streamed tile beyond the register tile, and in FP32
+// also for 384 < L <= 512, where the two split the unknowns alike (bit-identical
+// results) and the streamed tile, at two waves per SIMD, is the faster.
+__host__ __device__ inline bool auto_stream(int n, int l, int precision)
+{
+    return precision == L1LS_FP32 && (!mfma_tile_shape(n, l) || l > 384);
+}
 __host__ __device__ inline int64_t stream_groups_for(int64_t p)
 {
     const int64_t tiles = (p + 15) / 16;

@@ -47,8 +47,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // Autotuner: per (device, n, l, precision, refinement mode) the fastest of the
 // iteration tilings that exist for the shape (the MFMA tile with A in LDS or
-// from L2, 32 or 64 unknowns a wave for short stacks; beyond it the streamed
-// tile; and the wave-per-pixel kernel), timed on a synthetic stack of that shape.  Results are kept for the
+// from L2, 32 or 64 unknowns a wave for short stacks; the streamed tile; and the
+// wave-per-pixel kernel), timed on a synthetic stack of that shape.  Results are kept for the
 // process and in a text cache file (one "device n l precision mode family T KB
 // alds waves nc" line per shape): $L1LS_TUNE_CACHE, else
 // $XDG_CACHE_HOME/l1ls/tune.txt, else $HOME/.cache/l1ls/tune.txt; "off" disables it.
@@ -162,8 +162,8 @@ IterVariant autotune(int n, int l, const l1ls_options &opt, int dev)
     for (int alt = 0; alt < 3; ++alt)
         if (mfma_supports(n, l) && iter_variant(n, l, opt.precision, kMfma, alt, &probe))
             cands.push_back({kMfma, alt});
-    // beyond the register tile: the streamed tile (FP32, as the wave kernel)
-    if (!mfma_supports(n, l) && opt.precision == L1LS_FP32 && iter_variant(n, l, opt.precision, kStream, 0, &probe))
+    // the streamed tile (FP32, as the wave kernel)
+    if (opt.precision == L1LS_FP32 && iter_variant(n, l, opt.precision, kStream, 0, &probe))
         cands.push_back({kStream, 0});
     if (opt.precision == L1LS_FP32) cands.push_back({kWave, 0});  // the wave kernel is FP32 only
     IterVariant best_v;

@@ -139,9 +139,20 @@ def test_iteration_kernel_option(L):
     assert st == 0 and st2 == 0 and auto_big - wave_big == 512 * 1024 * 512
     o.iteration_kernel = 3  # streamed tile on a register-tile shape: 7 tiles of 16 pixels
     _, s_small = _ws(L, 50, 512, 100, o)
+    o.iteration_kernel = 1
+    _, m_small = _ws(L, 50, 512, 100, o)
+    assert s_small - m_small == 7 * 512 * 512
+    # the automatic choice: the streamed tile in FP32 for 384 < l <= 512, the
+    # register tile up to l = 384
     o.iteration_kernel = 0
-    _, a_small = _ws(L, 50, 512, 100, o)
-    assert s_small - a_small == 7 * 512 * 512
+    assert _ws(L, 50, 512, 100, o)[1] == s_small
+    o.iteration_kernel = 1
+    _, m_mid = _ws(L, 50, 384, 100, o)
+    o.iteration_kernel = 0
+    assert _ws(L, 50, 384, 100, o)[1] == m_mid
+    o.precision = 1
+    assert _ws(L, 50, 512, 100, o)[1] == m_small
+    o.precision = 0
     o.iteration_kernel = 1  # the register tile takes n <= 64, l <= 512 only
     assert _ws(L, 65, 256, 1, o)[0] == -2
     assert _solve(L, n=50, l=600, o=o, wsb=1 << 26) == -2
