@@ -74,8 +74,8 @@ typedef enum { L1LS_FP32 = 0, L1LS_SPLIT_BF16 = 1 } l1ls_precision;
  *  MFMA    the register-resident MFMA tile (n <= 64, l <= 512)
  *  WAVE    the wave-per-pixel kernel (plain FP32 vector arithmetic; FP32 only)
  *  STREAM  the streamed MFMA tile: the same FP32 contractions as the register
- *          tile, with each 16-pixel tile's iterate (x^k, x^{k-1}, G_k, G_{k-1})
- *          kept in the workspace (l_pad x 512 bytes a persistent workgroup, at
+ *          tile, with each 16-pixel tile's iterates and gradients (two x and
+ *          three G arrays) kept in the workspace (l_pad x 640 bytes a persistent workgroup, at
  *          most 512 of them); FP32 only, any supported shape
  * A kernel that does not take the shape or precision is refused with
  * L1LS_ERR_UNSUPPORTED_SHAPE.  The three agree to FP32 rounding; the register

@@ -12,16 +12,19 @@
 // blocks, as the register tile's waves do, so that where both tiles exist they
 // give bit-identical results.
 //
-// What differs is where the iterate lives.  A tile of 16 pixel slots keeps
-// x^k, x^{k-1}, G_k and G_{k-1} in a workspace slot of its own (l_pad x 512
-// bytes: 512 KB at 1,024 bins, more than a CU's registers and LDS together),
-// streamed one block (16 unknowns x 16 slots, 2 KB an array) at a time through
-// each pass of an iteration:
-//   trial       reads x^k, x^{k-1}, G_k, G_{k-1}; forms d = x-bar - y, A d
-//   acceptance  reads them again, recomputes x-bar, writes x^{k+1}
-//   adjoint     writes G_{k+1} = 2 A^H r_{k+1}
-// x and G are ping-pong pairs with a selector per slot, so the rotation
-// x^{k-1} <- x^k, G_{k-1} <- G_k moves no data.  Within a block, lane
+// What differs is where the iterate lives.  A tile of 16 pixel slots keeps its
+// iterates and gradients in a workspace slot of its own (two x arrays and three
+// G arrays, l_pad x 640 bytes: 640 KB at 1,024 bins, more than a CU's registers
+// and LDS together), streamed one block (16 unknowns x 16 slots, 2 KB an array)
+// at a time.  The acceptance of iteration k only decides (from the residuals,
+// which stay on chip); x^{k+1} is formed in the first trial pass of iteration
+// k + 1, which recomputes x-bar of iteration k from the same inputs:
+//   trial       reads x^k, x^{k-1}, G_{k+1}, G_k, G_{k-1}; writes x^{k+1} over
+//               x^{k-1}; forms d = x-bar - y and A d for iteration k + 1
+//   adjoint     writes G_{k+1} = 2 A^H r_{k+1} over G_{k-2}
+// (five reads and two writes an iteration; a repeated trial of Eq. (15) reads
+// the four arrays of its own iteration).  The x arrays are a pair and the G
+// arrays a ring of three, addressed per slot, so no rotation moves data.  Within a block, lane
 // (j = lane % 16, h = lane / 16) holds unknowns 16 b + 4 h + q, q = 0..3, of
 // slot j, the output layout of the MFMA; the lane's four complex values are
 // 32 contiguous bytes, so a wave reads or writes one array's block as 2 KB.
@@ -113,7 +116,13 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
         }
 
     int64_t pix = -1;
-    int k = 1, sel = 0;  // sel: which array of each pair holds x^k and G_k
+    // per slot: iteration k; xs, the x array holding the stored iterate (x^k, or
+    // x^{k-1} while the acceptance of iteration k-1 is pending), the other holding
+    // the one before; rot, the G array (of 2 + 0..2) holding G_k, (rot + 2) % 3
+    // G_{k-1} and (rot + 1) % 3 G_{k-2}; pend, acc, beta_p: the pending acceptance
+    int k = 1, xs = 0, rot = 0;
+    bool pend = false, acc = false;
+    float beta_p = 0.0f;
     float alpha = alpha0, lam = 1.0f, Fk = 0.0f;
     bool active = false, bad = false, qdone = false;
     unsigned long long n_fwd = 0, n_adj = 0;
@@ -223,7 +232,9 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
         if (fresh) {
             active = true;
             k = 1;
-            sel = 0;
+            xs = 0;
+            rot = 0;
+            pend = false;
             alpha = alpha0;
             lam = a.lambda[pix * a.lambda_stride];
             bad = !(lam > 0.0f) || !isfinite(lam);
@@ -251,7 +262,7 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
                 for (int b = b_lo; b < b_hi; ++b) {
                     fs::st_blk(fs::blk(st, NB, 0, b, lane), zero, zero);
                     fs::st_blk(fs::blk(st, NB, 1, b, lane), zero, zero);
-                    fs::st_blk(fs::blk(st, NB, 3, b, lane), zero, zero);
+                    fs::st_blk(fs::blk(st, NB, 4, b, lane), zero, zero);
                 }
             }
             return;
@@ -276,7 +287,7 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
             if (fresh) {
                 fs::st_blk(fs::blk(st, NB, 0, b, lane), xr, xi);
                 fs::st_blk(fs::blk(st, NB, 1, b, lane), xr, xi);
-                fs::st_blk(fs::blk(st, NB, 3, b, lane), zero, zero);
+                fs::st_blk(fs::blk(st, NB, 4, b, lane), zero, zero);
             }
             // W_re += A_re x_re - A_im x_im;  W_im += A_im x_re + A_re x_im
             f4 a01[T], a23[T];
@@ -302,7 +313,7 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
         n_fwd += __popcll(__ballot(fresh && h == 0));
     };
 
-    // ---- G_k = 2 A^H r_k for the wave's blocks (all slots), into the pair's `sel` array
+    // ---- G_k = 2 A^H r_k for the wave's blocks (all slots), into G array `rot`
     // (a block's A operands are all issued before its products)
     auto adj_load = [&](int b, float2 (&av)[T][4]) {
         const int m = 16 * b + j;
@@ -329,7 +340,7 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
                     gi = fm::mfma(av[t][q].y, npr, gi);
                 }
             const float g_r[4] = {gr[0], gr[1], gr[2], gr[3]}, g_i[4] = {gi[0], gi[1], gi[2], gi[3]};
-            fs::st_blk(fs::blk(st, NB, 2 + sel, b, lane), g_r, g_i);
+            fs::st_blk(fs::blk(st, NB, 2 + rot, b, lane), g_r, g_i);
         }
     };
 
@@ -344,8 +355,9 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
         bool first = true, retire = false, conv = false, nonfinite = false;
         float kkt = 0.0f, l1 = 0.0f;
         f4 Wr[T], Wi[T];
-        const int xs = sel, xps = 1 - sel, gs = 2 + sel, gps = 3 - sel;
+        const int gs = 2 + rot, gps = 2 + (rot == 0 ? 2 : rot - 1), gqs = 2 + (rot == 2 ? 0 : rot + 1);
         for (int trial = 0; trial < 64; ++trial) {
+            const bool anyp = __ballot(pend) != 0;  // wave-uniform: a slot's lanes agree
             n_fwd += __popcll(__ballot(active && h == 0));
             const float tau = alpha * lam;
             const float tk = lam * inv_lf;
@@ -357,9 +369,35 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
                 fwd_load(b, a01, a23);
                 float x_r[4], x_i[4], xp_r[4], xp_i[4], g_r[4], g_i[4], gp_r[4], gp_i[4];
                 fs::ld_blk(fs::blk(st, NB, xs, b, lane), x_r, x_i);
-                fs::ld_blk(fs::blk(st, NB, xps, b, lane), xp_r, xp_i);
+                fs::ld_blk(fs::blk(st, NB, 1 - xs, b, lane), xp_r, xp_i);
                 fs::ld_blk(fs::blk(st, NB, gs, b, lane), g_r, g_i);
                 fs::ld_blk(fs::blk(st, NB, gps, b, lane), gp_r, gp_i);
+                if (anyp) {
+                    // the pending acceptance of iteration k - 1: its x-bar recomputed from
+                    // x^{k-1}, x^{k-2}, G_{k-1}, G_{k-2} with its step, and x^k (x-bar if
+                    // accepted, else x^{k-1}) stored over x^{k-2}
+                    float gq_r[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gq_i[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (pend) fs::ld_blk(fs::blk(st, NB, gqs, b, lane), gq_r, gq_i);
+                    float o_r[4], o_i[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float y_r, y_i, xb_r, xb_i, axb;
+                        fm::trial_one(x_r[q], x_i[q], xp_r[q], xp_i[q], gp_r[q], gp_i[q], gq_r[q], gq_i[q],
+                                      beta_p, alpha, alpha * lam, y_r, y_i, xb_r, xb_i, axb);
+                        o_r[q] = acc ? xb_r : x_r[q];
+                        o_i[q] = acc ? xb_i : x_i[q];
+                    }
+                    if (pend) {
+                        fs::st_blk(fs::blk(st, NB, 1 - xs, b, lane), o_r, o_i);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            xp_r[q] = x_r[q];
+                            xp_i[q] = x_i[q];
+                            x_r[q] = o_r[q];
+                            x_i[q] = o_i[q];
+                        }
+                    }
+                }
                 if (trial == 0) {
                     // natural KKT residual of x^k with its exact gradient G_k
 #pragma unroll
@@ -385,6 +423,10 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
                     s1 += axb - __builtin_amdgcn_sqrtf(fmaf(x_r[q], x_r[q], x_i[q] * x_i[q]));
                 }
                 fwd_mfma(a01, a23, dr, di, Wr, Wi);
+            }
+            if (pend) {  // x^k is stored now
+                xs ^= 1;
+                pend = false;
             }
             d2 = fm::sum_h(d2);
             s1 = fm::sum_h(s1);
@@ -497,29 +539,6 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
             const float dF = fmaf(lam, l1, dfr);
             const bool live = active && !retire;
             const bool accept = live && (!a.monotone || dF <= 0.0f);
-            if (__ballot(live) != 0) {
-                // x^{k+1} (x-bar of the last trial, recomputed from the same inputs, or
-                // x^k) into the pair's other array, which held x^{k-1}
-                const float tau = alpha * lam;
-                for (int b = b_lo; b < b_hi; ++b) {
-                    if (!live) continue;
-                    float x_r[4], x_i[4], xp_r[4], xp_i[4], g_r[4], g_i[4], gp_r[4], gp_i[4];
-                    fs::ld_blk(fs::blk(st, NB, xs, b, lane), x_r, x_i);
-                    fs::ld_blk(fs::blk(st, NB, xps, b, lane), xp_r, xp_i);
-                    fs::ld_blk(fs::blk(st, NB, gs, b, lane), g_r, g_i);
-                    fs::ld_blk(fs::blk(st, NB, gps, b, lane), gp_r, gp_i);
-                    float o_r[4], o_i[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        float y_r, y_i, xb_r, xb_i, axb;
-                        fm::trial_one(x_r[q], x_i[q], xp_r[q], xp_i[q], g_r[q], g_i[q], gp_r[q], gp_i[q],
-                                      beta, alpha, tau, y_r, y_i, xb_r, xb_i, axb);
-                        o_r[q] = accept ? xb_r : x_r[q];
-                        o_i[q] = accept ? xb_i : x_i[q];
-                    }
-                    fs::st_blk(fs::blk(st, NB, xps, b, lane), o_r, o_i);
-                }
-            }
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -532,8 +551,13 @@ __device__ __forceinline__ void fista_stream_stack(const FistaArgs &a, float2 *s
                 }
             if (accept) Fk += dF;
             if (live) {
+                // x^{k+1} is formed in the next trial pass (the step and the decision
+                // are kept); G_{k+1} goes over G_{k-2}
+                pend = true;
+                acc = accept;
+                beta_p = beta;
                 ++k;
-                sel ^= 1;
+                rot = rot == 2 ? 0 : rot + 1;
             }
         }
 

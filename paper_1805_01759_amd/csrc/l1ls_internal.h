@@ -134,8 +134,8 @@ __host__ __device__ inline int rows_pad_for(int n) { return 16 * ((n + 15) / 16)
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) / 256 * 256; }
 
 // The register-resident MFMA tile takes up to 64 rows and 512 bins; larger shapes
-// run the streamed MFMA tile, whose iterate state (x^k, x^{k-1}, G_k, G_{k-1} of
-// 16 pixels: l_pad x 512 bytes a tile) lives in a workspace region, one slot per
+// run the streamed MFMA tile, whose iterate state (two x and three G arrays of 16
+// pixels: l_pad x 640 bytes a tile) lives in a workspace region, one slot per
 // persistent workgroup (at most kStreamGroups of them).
 __host__ __device__ inline bool mfma_tile_shape(int n, int l) { return n <= 64 && l <= 512; }
 constexpr int kStreamGroups = 512;
@@ -151,7 +151,7 @@ __host__ __device__ inline int64_t stream_groups_for(int64_t p)
     const int64_t tiles = (p + 15) / 16;
     return tiles < kStreamGroups ? tiles : kStreamGroups;
 }
-__host__ __device__ inline size_t stream_tile_bytes(int l_pad) { return (size_t)l_pad * 512; }
+__host__ __device__ inline size_t stream_tile_bytes(int l_pad) { return (size_t)l_pad * 640; }
 
 // Workspace layout for one stack (byte offsets; every region 256-byte aligned).
 struct StackWorkspace {

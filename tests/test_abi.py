@@ -130,18 +130,18 @@ def test_split_bf16_refused_without_an_mfma_kernel(L):
 
 def test_iteration_kernel_option(L):
     # the streamed MFMA tile keeps each persistent workgroup's iterate in the workspace:
-    # l_pad x 512 bytes for each of min(tiles of 16 pixels, 512) workgroups
+    # l_pad x 640 bytes for each of min(tiles of 16 pixels, 512) workgroups
     o = L.l1ls_options_default()
     assert o.iteration_kernel == 0
     st, auto_big = _ws(L, 100, 1024, 1 << 16, o)
     o.iteration_kernel = 2  # the wave kernel keeps no such state
     st2, wave_big = _ws(L, 100, 1024, 1 << 16, o)
-    assert st == 0 and st2 == 0 and auto_big - wave_big == 512 * 1024 * 512
+    assert st == 0 and st2 == 0 and auto_big - wave_big == 512 * 1024 * 640
     o.iteration_kernel = 3  # streamed tile on a register-tile shape: 7 tiles of 16 pixels
     _, s_small = _ws(L, 50, 512, 100, o)
     o.iteration_kernel = 1
     _, m_small = _ws(L, 50, 512, 100, o)
-    assert s_small - m_small == 7 * 512 * 512
+    assert s_small - m_small == 7 * 512 * 640
     # the automatic choice: the streamed tile in FP32 for 384 < l <= 512, the
     # register tile up to l = 384
     o.iteration_kernel = 0
