@@ -53,7 +53,8 @@ KERNEL_SOURCES = {
     "fista_mfma_kernel": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
     "fista_mfma_kernel_bf16": ("fista_mfma.h", "fista.hip", "l1ls_internal.h"),
     "fista_wave_kernel": ("fista_wave.hip", "l1ls_internal.h"),
-    "fista_stream_kernel": ("fista_stream.hip", "fista_mfma.h", "l1ls_internal.h"),
+    "fista_stream_kernel": ("fista_stream.h", "fista_mfma.h", "l1ls_internal.h"),
+    "fista_stream_kernel_bf16": ("fista_stream.h", "fista_mfma.h", "l1ls_internal.h"),
     "polish_kernel": ("polish.hip", "wave_reduce.h", "l1ls_internal.h"),
     "certify_kernel": ("certify.hip", "wave_reduce.h", "l1ls_internal.h"),
 }
@@ -371,7 +372,8 @@ def run_precision(api, Ad, Bd, ld, X, ws, n, l, p, prec, steps, warmup, args, sa
     import torch
     opts = dict(max_iter=args.max_iter, tol=1e-4, precision=prec, fp64_polish=args.polish,
                 polish_after=args.polish_after, fp64_continue=args.fp64_continue,
-                iteration_kernel=args.iteration_kernel if prec == "fp32" else "auto")
+                iteration_kernel=("auto" if prec != "fp32" and args.iteration_kernel == "wave"
+                                  else args.iteration_kernel))
     for _ in range(warmup):
         api.solve(Ad, Bd, ld, out=X, workspace=ws, **opts)
     torch.cuda.synchronize()
@@ -431,7 +433,9 @@ def rooflines(r, n, l, prec, workload, polish, kernel="auto"):
     """Roofline objects of the iteration and refinement kernels of one run."""
     avg_s = r["avg_s"]
     if prec != "fp32":
-        it_kernel = "fista_mfma_kernel_bf16"
+        # split-BF16: the automatic choice as in FP32 (the streamed tile beyond 384 bins)
+        stream = kernel == "stream" or (kernel != "mfma" and not (n <= 64 and l <= 384))
+        it_kernel = "fista_stream_kernel_bf16" if stream else "fista_mfma_kernel_bf16"
     elif kernel != "auto":
         it_kernel = f"fista_{kernel}_kernel"
     elif n <= 64 and l <= 384:
@@ -546,11 +550,8 @@ def main():
     sample_idx = (np.arange(ps, dtype=np.int64) * p) // max(ps, 1) + (p // max(ps, 1)) // 2 \
         if ps else np.zeros(0, np.int64)
     other = "split_bf16" if args.precision == "fp32" else "fp32"
-    if "split_bf16" in (args.precision, other) and not (n <= 64 and l <= 512):
-        if args.precision == "split_bf16":
-            sys.exit(f"split-BF16 needs n <= 64 and l <= 512 (the MFMA kernels); this workload has "
-                     f"n = {n}, l = {l}")
-        other = None  # the wave-per-pixel kernel computes in FP32 only
+    if args.precision == "split_bf16" and args.iteration_kernel == "wave":
+        sys.exit("split-BF16 runs on the MFMA tiles only (not the wave-per-pixel kernel)")
     runs = {args.precision: run_precision(api, Ad, Bd, ld, X, ws, n, l, p, args.precision,
                                           args.steps, args.warmup, args, sample_idx,
                                           keep_x=sr_meta is not None)}
@@ -602,7 +603,9 @@ def main():
                                       "cases": rates}
     if other:
         o = runs[other]
-        o_it, o_rf = rooflines(o, n, l, other, args.workload, args.polish)
+        o_it, o_rf = rooflines(o, n, l, other, args.workload, args.polish,
+                               "auto" if other != "fp32" and args.iteration_kernel == "wave"
+                               else args.iteration_kernel)
         rec["compare"] = {"precision": other, "value": o["value"], "unit": "pixels/s",
                           "steps": max(1, min(args.steps, args.compare_steps)),
                           "ms_per_step": o["ms_per_step"], "solved_fraction": o["solved_fraction"],

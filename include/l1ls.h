@@ -57,29 +57,30 @@ typedef enum {
  * L1LS_FP32: FP32 MFMA.  L1LS_SPLIT_BF16: every operand split into hi + lo
  * bfloat16 parts, three MFMA passes (hi*hi + hi*lo + lo*hi) with FP32
  * accumulation.  Everything else (prox, step, reductions) is FP32; the
- * refinement and the final optimality check are FP64.  Split-BF16 exists in the
- * register-resident MFMA tile only (n <= 64, l <= 512): larger shapes (the
- * streamed MFMA tile or the wave-per-pixel kernel), the block form and the
- * iteration kernels STREAM and WAVE take L1LS_FP32 only and refuse
- * L1LS_SPLIT_BF16 (L1LS_ERR_UNSUPPORTED_SHAPE, also from l1ls_workspace_size and
+ * refinement and the final optimality check are FP64.  Split-BF16 runs on the
+ * MFMA tiles (the register-resident tile and the streamed tile, which takes every
+ * supported shape); the wave-per-pixel kernel (iteration_kernel WAVE) and the
+ * block form take L1LS_FP32 only and refuse L1LS_SPLIT_BF16
+ * (L1LS_ERR_UNSUPPORTED_SHAPE, also from l1ls_workspace_size and
  * l1ls_plan_create). */
 typedef enum { L1LS_FP32 = 0, L1LS_SPLIT_BF16 = 1 } l1ls_precision;
 
 /* The kernel that runs the iterations of Algorithm 1 (l1ls_options.iteration_kernel).
- *  AUTO    in FP32 the streamed MFMA tile, except for n <= 64 and l <= 384,
- *          which run the register-resident tile (as split-BF16 does for every
- *          n <= 64, l <= 512); l1ls_plan_create times the candidates instead, and
- *          l1ls_solve_noalloc takes the register tile where the streamed tile's
- *          state would not fit its scratch
+ *  AUTO    the streamed MFMA tile, except for n <= 64 and l <= 384, which run
+ *          the register-resident tile; l1ls_plan_create times the candidates
+ *          instead, and l1ls_solve_noalloc takes the register tile where the
+ *          streamed tile's state would not fit its scratch
  *  MFMA    the register-resident MFMA tile (n <= 64, l <= 512)
  *  WAVE    the wave-per-pixel kernel (plain FP32 vector arithmetic; FP32 only)
- *  STREAM  the streamed MFMA tile: the same FP32 contractions as the register
- *          tile, with each 16-pixel tile's iterates and gradients (two x and
- *          three G arrays) kept in the workspace (l_pad x 640 bytes a persistent workgroup, at
- *          most 512 of them); FP32 only, any supported shape
+ *  STREAM  the streamed MFMA tile: the same contractions as the register tile
+ *          (FP32 or split-BF16), with each 16-pixel tile's iterates and
+ *          gradients (two x and three G arrays) kept in the workspace (l_pad x
+ *          640 bytes a persistent workgroup, at most 512 of them); any
+ *          supported shape
  * A kernel that does not take the shape or precision is refused with
  * L1LS_ERR_UNSUPPORTED_SHAPE.  The three agree to FP32 rounding; the register
- * and streamed tiles give bit-identical results for 384 < l <= 512. */
+ * and streamed tiles give bit-identical results for 384 < l <= 512, in either
+ * precision. */
 typedef enum {
     L1LS_ITER_AUTO = 0,
     L1LS_ITER_MFMA = 1,

@@ -87,16 +87,12 @@ static l1ls_status check_shape(int32_t n, int32_t l, int64_t p)
     return L1LS_OK;
 }
 
-// Split-BF16 contractions exist in the MFMA kernels only; the shapes those do
-// not take (the wave-per-pixel kernel) refuse it rather than run FP32.
+// Split-BF16 contractions exist in the MFMA tiles only; the wave-per-pixel
+// kernel refuses it rather than run FP32.
 static l1ls_status check_precision(int32_t n, int32_t l, const l1ls_options *o)
 {
-    if (o->precision == L1LS_SPLIT_BF16 && !mfma_supports(n, l))
-        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "split-BF16 needs n <= 64 and l <= 512 (got n = %d, l = %d)", n,
-                    l);
-    if (o->precision == L1LS_SPLIT_BF16 &&
-        (o->iteration_kernel == L1LS_ITER_WAVE || o->iteration_kernel == L1LS_ITER_STREAM))
-        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "split-BF16 runs on the register-resident MFMA tile only");
+    if (o->precision == L1LS_SPLIT_BF16 && o->iteration_kernel == L1LS_ITER_WAVE)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "split-BF16 runs on the MFMA tiles only (not the wave kernel)");
     if (o->iteration_kernel == L1LS_ITER_MFMA && !mfma_supports(n, l))
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the register-resident MFMA tile needs n <= 64, l <= 512");
     return L1LS_OK;

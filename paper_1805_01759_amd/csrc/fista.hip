@@ -315,9 +315,9 @@ bool mfma_supports(int n, int l);
 // (L <= 256) or 128 unknowns a wave and up to four waves; A is staged in LDS
 // where it fits.  Split-BF16 stages its bf16 planes of A in LDS where they fit,
 // else reads them from L2.  Shapes beyond the register tile (N > 64 or L > 512)
-// run the streamed MFMA tile (FP32), and so does kAuto in FP32 for 384 < L <= 512
-// (auto_stream); choice kStream runs it for any shape, kWave the wave-per-pixel
-// kernel, kMfma the register tile.
+// run the streamed MFMA tile (either precision), and so does kAuto for
+// 384 < L <= 512 (auto_stream); choice kStream runs it for any shape, kWave the
+// wave-per-pixel kernel (FP32), kMfma the register tile.
 bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant *v)
 {
     IterVariant r{};
@@ -332,12 +332,12 @@ bool iter_variant(int n, int l, int precision, int choice, int alt, IterVariant 
         return r.nc > 0;
     }
     if (choice == kStream || (choice == kAuto && auto_stream(n, l, precision)) || !mfma_supports(n, l)) {
-        if (alt != 0 || precision != L1LS_FP32 || T > 8) return false;
+        if (alt != 0 || T > 8) return false;
         r.family = kVarStream;
         r.T = T;
         r.waves = 4;
         r.wmax = 4;
-        r.prec = L1LS_FP32;
+        r.prec = precision;
         *v = r;
         return true;
     }
@@ -413,7 +413,7 @@ static hipError_t launch_mfma_t(const StackTable &t, const IterVariant &v, hipSt
 hipError_t launch_iteration_table(const StackTable &t, const IterVariant &v, hipStream_t s)
 {
     if (v.family == kVarWave) return launch_wave_table(t, v.nc, s);
-    if (v.family == kVarStream) return launch_stream_table(t, v.T, s);
+    if (v.family == kVarStream) return launch_stream_table(t, v.T, v.prec, s);
     const bool bf = v.prec == L1LS_SPLIT_BF16;
     switch (v.T) {
     case 1: return bf ? launch_mfma_t<1, L1LS_SPLIT_BF16>(t, v, s) : launch_mfma_t<1, L1LS_FP32>(t, v, s);

@@ -139,12 +139,12 @@ __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) / 256 * 
 // persistent workgroup (at most kStreamGroups of them).
 __host__ __device__ inline bool mfma_tile_shape(int n, int l) { return n <= 64 && l <= 512; }
 constexpr int kStreamGroups = 512;
-// The automatic choice: the streamed tile beyond the register tile, and in FP32
-// also for 384 < L <= 512, where the two split the unknowns alike (bit-identical
-// results) and the streamed tile, at two waves per SIMD, is the faster.
-__host__ __device__ inline bool auto_stream(int n, int l, int precision)
+// The automatic choice: the streamed tile beyond the register tile, and also for
+// 384 < L <= 512, where the two split the unknowns alike (bit-identical results,
+// either precision) and the streamed tile, at two waves per SIMD, is the faster.
+__host__ __device__ inline bool auto_stream(int n, int l, int /*precision*/)
 {
-    return precision == L1LS_FP32 && (!mfma_tile_shape(n, l) || l > 384);
+    return !mfma_tile_shape(n, l) || l > 384;
 }
 __host__ __device__ inline int64_t stream_groups_for(int64_t p)
 {
@@ -423,6 +423,6 @@ hipError_t launch_unrolled_backward(int n, int l, int64_t p, const float2 *B, fl
                                     void *ws, hipStream_t st);
 size_t fista_mfma_lds_bytes(int n, int l_pad, int waves, bool a_lds, int precision);
 size_t fista_stream_lds_bytes(int T);
-hipError_t launch_stream_table(const StackTable &t, int T, hipStream_t s);
+hipError_t launch_stream_table(const StackTable &t, int T, int precision, hipStream_t s);
 
 }  // namespace l1ls

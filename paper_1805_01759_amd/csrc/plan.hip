@@ -100,7 +100,7 @@ void tune_load_locked()
         l1ls_options o{};
         o.precision = prec;
         o.fp64_polish = mode;
-        v.prec = v.family == kVarMfma ? prec : L1LS_FP32;
+        v.prec = v.family == kVarWave ? L1LS_FP32 : prec;
         v.wmax = v.family == kVarMfma && v.KB == 2 ? 8 : 4;
         g_tune_cache[tune_key(dev, n, l, o)] = v;
     }
@@ -162,9 +162,8 @@ IterVariant autotune(int n, int l, const l1ls_options &opt, int dev)
     for (int alt = 0; alt < 3; ++alt)
         if (mfma_supports(n, l) && iter_variant(n, l, opt.precision, kMfma, alt, &probe))
             cands.push_back({kMfma, alt});
-    // the streamed tile (FP32, as the wave kernel)
-    if (opt.precision == L1LS_FP32 && iter_variant(n, l, opt.precision, kStream, 0, &probe))
-        cands.push_back({kStream, 0});
+    // the streamed tile (either precision)
+    if (iter_variant(n, l, opt.precision, kStream, 0, &probe)) cands.push_back({kStream, 0});
     if (opt.precision == L1LS_FP32) cands.push_back({kWave, 0});  // the wave kernel is FP32 only
     IterVariant best_v;
     iter_variant(n, l, opt.precision, cands[0].first, cands[0].second, &best_v);

@@ -110,18 +110,19 @@ def test_warm_start_refused_where_unsupported(L):
 
 
 def test_split_bf16_refused_without_an_mfma_kernel(L):
-    # split-BF16 exists in the MFMA kernels (n <= 64, l <= 512) only: the wave-per-pixel
-    # shapes and the block form refuse it instead of computing in FP32
+    # split-BF16 exists in the MFMA tiles (the register tile up to n = 64, l = 512,
+    # the streamed tile for every supported shape); the wave-per-pixel kernel and
+    # the block form refuse it instead of computing in FP32
     o = L.l1ls_options_default()
     o.precision = 1
-    assert _ws(L, 64, 512, 1, o)[0] == 0
-    for n, l in ((65, 256), (50, 513), (128, 1024)):
+    for n, l in ((64, 512), (65, 256), (50, 513), (128, 1024)):
+        assert _ws(L, n, l, 1, o)[0] == 0
+    o.iteration_kernel = 2
+    for n, l in ((20, 100), (128, 1024)):
         assert _ws(L, n, l, 1, o)[0] == -2
         assert b"split-BF16" in L.l1ls_last_error()
         assert _solve(L, n=n, l=l, o=o, wsb=1 << 26) == -2
-    o.precision = 0
-    assert _ws(L, 128, 1024, 1, o)[0] == 0
-    o.precision = 1
+    o.iteration_kernel = 0
     st = L.l1ls_solve_blocks(4, 8, 3, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(64), 0,
                              ctypes.byref(o), 2, ctypes.c_void_p(512), ctypes.c_void_p(128), None,
                              ctypes.c_void_p(256), 1 << 20, None)
@@ -150,8 +151,9 @@ def test_iteration_kernel_option(L):
     _, m_mid = _ws(L, 50, 384, 100, o)
     o.iteration_kernel = 0
     assert _ws(L, 50, 384, 100, o)[1] == m_mid
-    o.precision = 1
-    assert _ws(L, 50, 512, 100, o)[1] == m_small
+    o.precision = 1  # the same choice in split-BF16
+    assert _ws(L, 50, 512, 100, o)[1] == s_small
+    assert _ws(L, 50, 384, 100, o)[1] == m_mid
     o.precision = 0
     o.iteration_kernel = 1  # the register tile takes n <= 64, l <= 512 only
     assert _ws(L, 65, 256, 1, o)[0] == -2
@@ -160,11 +162,15 @@ def test_iteration_kernel_option(L):
     o.iteration_kernel = 4
     assert _ws(L, 10, 10, 1, o)[0] == -1
     assert _solve(L, o=o) == -1
-    o.precision = 1  # split-BF16 only on the register tile
-    for k in (2, 3):
-        o.iteration_kernel = k
-        assert _ws(L, 50, 512, 1, o)[0] == -2
-        assert b"split-BF16" in L.l1ls_last_error()
+    o.precision = 1  # split-BF16 on the MFMA tiles, not the wave kernel
+    o.iteration_kernel = 2
+    assert _ws(L, 50, 512, 1, o)[0] == -2
+    assert b"split-BF16" in L.l1ls_last_error()
+    o.iteration_kernel = 3
+    assert _ws(L, 50, 512, 1, o)[0] == 0
+    o.iteration_kernel = 0  # beyond the register tile the streamed tile takes split-BF16 too
+    _, bf_big = _ws(L, 100, 1024, 1 << 16, o)
+    assert bf_big == auto_big
     o.precision = 0
     o.iteration_kernel = 3
     assert _solve(L, o=o, wsb=16) == -3  # workspace checked against the streamed tile's size

@@ -22,13 +22,13 @@ def _stack(ss):
     return synth.to_device_dtypes(geom.A, B, lam)
 
 
-@pytest.mark.parametrize("kernel", ["auto", "wave"])
+@pytest.mark.parametrize("kernel,precision", [("auto", "fp32"), ("wave", "fp32"), ("auto", "split_bf16")])
 @pytest.mark.parametrize("n,l,p", [(100, 1024, 24), (80, 300, 40), (128, 64, 20), (11, 700, 33)])
-def test_large_shapes(dev, orc, n, l, p, kernel):
+def test_large_shapes(dev, orc, n, l, p, kernel, precision):
     ss = synth.StackSpec(90 + n % 7, n, l, p)
     A, B, lam = _stack(ss)
     Ad, Bd, ld = (torch.from_numpy(x).to(dev) for x in (A, B, lam))
-    X, d = api.solve(Ad, Bd, ld, fp64_polish=2, polish_after=100, iteration_kernel=kernel)
+    X, d = api.solve(Ad, Bd, ld, fp64_polish=2, polish_after=100, iteration_kernel=kernel, precision=precision)
     A64, B64, L64 = A.astype(complex), B.astype(complex), lam.astype(float)
     Xe, de = orc.exact_batch(A64, B64, L64)
     Xg = X.cpu().numpy().astype(complex)

@@ -83,7 +83,8 @@ def test_motion_trajectory_parity(dev, orc, cfg):
     assert np.array_equal(d["iters"].cpu().numpy(), do["iters"])
 
 
-@pytest.mark.parametrize("cfg,prec,bar", [(6, "fp32", 1e-4), (6, "split_bf16", 1e-3), (7, "fp32", 1e-4)])
+@pytest.mark.parametrize("cfg,prec,bar", [(6, "fp32", 1e-4), (6, "split_bf16", 1e-3), (7, "fp32", 1e-4),
+                                          (7, "split_bf16", 1e-3)])
 def test_motion_solve_matches_minimiser(dev, orc, cfg, prec, bar):
     """Bench settings (FP64 stage after the FP32 budget) on a ragged pixel count."""
     p = 1000 if cfg == 6 else 333
