@@ -77,3 +77,28 @@ def test_noalloc_rejects_beyond_its_scratch():
     L = _lib.load()
     o = L.l1ls_options_default()
     assert L.l1ls_solve_noalloc(n, l, 0, None, None, None, 0, ctypes.byref(o), None, None, None) == 0
+
+
+def test_noalloc_register_tile_fallback():
+    """At 20,000 close pairs the streamed tile's iterate slots (512 workgroups x 320 KB)
+    do not fit the scratch: the automatic choice of l1ls_solve_noalloc takes the
+    register tile there, while l1ls_solve runs the streamed tile; the two tiles give
+    the same results bit for bit at L = 512."""
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    dev = torch.device("cuda:0")
+    print("noalloc: close-pair stack, 20000 pixels (register-tile fallback)", flush=True)
+    A, B, lam = _inputs(4, 20000, dev)
+    n, l, p = A.shape[0], A.shape[1], B.shape[0]
+    o = api.options(polish_after=4)
+    L = _lib.load()
+    sz = ctypes.c_size_t(0)
+    assert L.l1ls_workspace_size(n, l, p, ctypes.byref(o), ctypes.byref(sz)) == 0
+    assert sz.value > _lib.NOALLOC_SCRATCH_BYTES  # the streamed tile's workspace
+    o.iteration_kernel = 1
+    assert L.l1ls_workspace_size(n, l, p, ctypes.byref(o), ctypes.byref(sz)) == 0
+    assert sz.value <= _lib.NOALLOC_SCRATCH_BYTES  # the register tile's
+    for prec in ("fp32", "split_bf16"):
+        X0, d0, X1, d1 = _both(A, B, lam, polish_after=4, precision=prec)
+        _same(X0, d0, X1, d1)
+        assert ((d1["status"] & 1) != 0).float().mean().item() > 0.99
