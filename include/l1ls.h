@@ -28,7 +28,11 @@
  *    returns a negative l1ls_status and l1ls_last_error() describes it.
  *  - Numerical outcomes are not errors: per-pixel results are reported in
  *    l1ls_diag.status and the call returns L1LS_OK.
- *  - Supported sizes: 1 <= N <= 128, 1 <= L <= 1024, 0 <= P < 2^31.
+ *  - Supported sizes: 1 <= N <= 128, 1 <= L <= 4096, 0 <= P < 2^31 (the
+ *    wave-per-pixel kernel, the FP64 continuation and the block form take up
+ *    to 1,024 bins: above that, WAVE is refused, fp64_continue leaves the
+ *    pixels a refinement pass cannot finish unsolved, and l1ls_solve_blocks
+ *    refuses blocks of more than 1,024 columns).
  */
 #ifndef L1LS_H
 #define L1LS_H

@@ -25,10 +25,12 @@ static l1ls_status fail(l1ls_status st, const char *fmt, ...)
     return st;
 }
 
-// Largest supported shapes: the register-resident MFMA kernel takes N <= 64,
-// L <= 512; the wave-per-pixel kernel takes the rest up to N = 128, L = 1024.
+// Largest supported shapes: the register-resident MFMA tile takes N <= 64,
+// L <= 512; the streamed MFMA tile every shape up to N = 128, L = 4096 (the
+// wave-per-pixel kernel up to L = 1024; the FP64 continuation and the block form
+// up to 1,024 bins, or columns a block).
 constexpr int kMaxNSolve = 128;
-constexpr int kMaxLSolve = 1024;
+constexpr int kMaxLSolve = 4096;
 
 bool mfma_supports(int n, int l) { return mfma_tile_shape(n, l); }
 
@@ -95,6 +97,8 @@ static l1ls_status check_precision(int32_t n, int32_t l, const l1ls_options *o)
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "split-BF16 runs on the MFMA tiles only (not the wave kernel)");
     if (o->iteration_kernel == L1LS_ITER_MFMA && !mfma_supports(n, l))
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the register-resident MFMA tile needs n <= 64, l <= 512");
+    if (o->iteration_kernel == L1LS_ITER_WAVE && l > 1024)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the wave-per-pixel kernel needs l <= 1024");
     return L1LS_OK;
 }
 
@@ -448,6 +452,8 @@ l1ls_status l1ls_solve_blocks(int32_t n, int32_t l, int64_t p, const l1ls_c32 *A
     if (opt && opt->precision == L1LS_SPLIT_BF16)
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the block form computes its products in FP32 only");
     if (!draws && p > 0) return fail(L1LS_ERR_INVALID_ARG, "draws is NULL");
+    if ((l + blocks - 1) / blocks > 1024)
+        return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "the block form takes blocks of at most 1024 columns");
     if (opt && fista_blocks_lds(n, lpad_for(l), blocks) > 64 * 1024)
         return fail(L1LS_ERR_UNSUPPORTED_SHAPE, "block form needs more than 64 KB of LDS per pixel");
     return solve_stack(n, l, p, A, B, lambda, lambda_stride, opt, X, diag, workspace, ws_bytes,

@@ -14,7 +14,9 @@ namespace l1ls {
 // of W <= 4 waves (one per SIMD) covers L <= 8 KB W.
 constexpr int kTile = 16;        // pixels per workgroup (MFMA N dimension)
 constexpr int kMaxWavesIter = 4;
-constexpr int kMaxWaves = 16;    // staging bound: L <= 1024
+// The FP64 continuation of Algorithm 1 keeps a pixel's iterate in registers, 16
+// chunks of 64 bins: stacks of more bins are not continued.
+constexpr int kContMaxL = 1024;
 constexpr int kMaxN = 128;
 constexpr int kMaxZB = 16;       // ceil(2 N / 16) <= 16
 
@@ -312,9 +314,10 @@ __host__ __device__ inline PolishArgsDev polish_args_for(const StackDesc &d, con
     pa.list = tier == 1 ? oflow : plist;
     pa.R = (tier == 0 && d.keep_residual) ? (const float2 *)(d.ws + lay.resid) : nullptr;
     // tier 2 lists the pixels it leaves above tol for the FP64 continuation
-    // (queue[7]), when that runs
-    pa.overflow = tier == 0 ? oflow : (tier == 1 ? plist : (o.cont ? oflow : nullptr));
-    pa.overflow_count = tier < 2 || o.cont ? queue + 3 + 2 * tier : nullptr;
+    // (queue[7]), when that runs (up to kContMaxL bins)
+    const bool cont = o.cont && lpad_for(d.l) <= kContMaxL;
+    pa.overflow = tier == 0 ? oflow : (tier == 1 ? plist : (cont ? oflow : nullptr));
+    pa.overflow_count = tier < 2 || cont ? queue + 3 + 2 * tier : nullptr;
     pa.status = (uint32_t *)(d.ws + lay.status);
     pa.work = (unsigned long long *)(d.ws + lay.work);
     pa.H = (const double2 *)(d.ws + lay.hgram);

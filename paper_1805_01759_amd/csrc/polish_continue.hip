@@ -321,7 +321,7 @@ template <int NC>
 __global__ void __launch_bounds__(64) continue_kernel(const StackTable t)
 {
     for (int i = 0; i < t.count; ++i) {
-        if (t.d[i].p <= 0) continue;
+        if (t.d[i].p <= 0 || lpad_for(t.d[i].l) > kContMaxL) continue;
         const ContinueArgs a = continue_args_for(t.d[i], t.o);
         continue_stack<NC>(a);
         __syncthreads();
@@ -354,7 +354,7 @@ hipError_t launch_continue_table(const StackTable &t, hipStream_t s)
     int lpmax = 0;
     int64_t want = 0;
     for (int i = 0; i < t.count; ++i) {
-        if (t.d[i].p <= 0) continue;
+        if (t.d[i].p <= 0 || lpad_for(t.d[i].l) > kContMaxL) continue;  // not continued
         const int lp = lpad_for(t.d[i].l);
         lds = std::max(lds, continue_lds(t.d[i].n, lp));
         lpmax = std::max(lpmax, lp);

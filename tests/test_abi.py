@@ -52,8 +52,12 @@ def test_workspace_sizes(L):
     assert _ws(L, 10, 10, -1)[0] == -1
     assert _ws(L, 129, 100, 1)[0] == -2
     assert b"supported sizes" in L.l1ls_last_error()
-    assert _ws(L, 10, 1025, 1)[0] == -2
-    assert _ws(L, 128, 1024, 1)[0] == 0
+    assert _ws(L, 10, 4097, 1)[0] == -2
+    assert _ws(L, 128, 4096, 1)[0] == 0
+    o = L.l1ls_options_default()
+    o.iteration_kernel = 2  # the wave-per-pixel kernel stops at 1,024 bins
+    assert _ws(L, 10, 1024, 1, o)[0] == 0
+    assert _ws(L, 10, 1025, 1, o)[0] == -2
 
 
 def _solve(L, n=4, l=8, p=3, o=None, A=16, B=32, lam=64, X=128, ws=256, wsb=1 << 20, stride=0):

@@ -27,8 +27,11 @@ def _t(dev, a):
 
 
 def _stack(n, l, p, seed_cfg=9):
-    geom = synth.make_geometry(seed_cfg, n, l, 250.0, -50.0, 50.0)
-    spec = synth.Spec(seed_cfg, n, l, p, 250.0, -50.0, 50.0, "c1", 10.0)
+    # elevations over [-50, 50] m, widened beyond 1,024 bins so that the bin spacing
+    # stays at the 0.1 m of the L = 1,024 grid
+    half = 50.0 * max(1.0, l / 1024.0)
+    geom = synth.make_geometry(seed_cfg, n, l, 250.0, -half, half)
+    spec = synth.Spec(seed_cfg, n, l, p, 250.0, -half, half, "c1", 10.0)
     B, lam = synth.make_pixels(spec, geom)
     return synth.to_device_dtypes(geom.A, B, lam)
 
@@ -68,7 +71,7 @@ def test_stream_bitwise_equals_register_tile(dev, n, l, p, mode, precision):
 
 # beyond the register tile: up to 8 row blocks, up to 1,024 bins, ragged N, L and P
 BEYOND = [(100, 1024, 24), (80, 300, 40), (128, 64, 20), (11, 700, 33), (70, 1000, 17), (65, 1, 5),
-          (1, 1024, 19), (120, 513, 31)]
+          (1, 1024, 19), (120, 513, 31), (50, 2048, 24), (40, 4096, 16), (128, 3000, 9)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
@@ -166,3 +169,19 @@ def test_stream_more_tiles_than_workgroups(dev, orc, n, l, p):
         assert (ko[conv[idx]] <= 1e-4 * (1 + 1e-5)).all(), kern
         objs.append(Fg)
     assert np.abs(objs[0] - objs[1]).max() <= 1e-4 * max(np.abs(objs[1]).max(), 1.0)
+
+
+@pytest.mark.parametrize("n,l,p", [(50, 2048, 40), (40, 4096, 20), (128, 3000, 17)])
+def test_grids_beyond_1024_bins_reach_the_minimiser(dev, orc, n, l, p):
+    """Beyond 1,024 bins (the streamed tile, the refinement with its bin Gram, the
+    certificate): with every pixel refined to FP64 accuracy each pixel is certified
+    and its objective is the oracle's minimum."""
+    A32, B32, l32 = _stack(n, l, p)
+    X, d = api.solve(_t(dev, A32), _t(dev, B32), _t(dev, l32), fp64_polish=2, polish_after=12)
+    A64, B64, L64 = A32.astype(np.complex128), B32.astype(np.complex128), l32.astype(np.float64)
+    Xe, de = orc.exact_batch(A64, B64, L64)
+    Xg = X.cpu().numpy().astype(np.complex128)
+    Fg = np.array([orc.objective(A64, B64[i], L64[i], Xg[i]) for i in range(p)])
+    gap = (Fg - de["objective"]) / np.maximum(de["objective"], 1.0)
+    conv = (d["status"].cpu().numpy() & _lib.PX_CONVERGED) != 0
+    assert conv.all() and gap.max() <= 1e-9, (conv.mean(), gap.max())
