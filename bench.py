@@ -40,6 +40,9 @@ WORKLOADS = {
                   "(L=512), P=524288, 0/1/2 scatterers (0.3/0.5/0.2) at off-grid (s, v), SNR U[0,20] dB"),
     "motion_fine": (7, "multicomponent TomoSAR stack as 'motion' with 64 elevation bins (L=1024), "
                        "P=65536"),
+    "motion_seasonal": (10, "multicomponent TomoSAR stack (elevation x linear velocity x seasonal "
+                            "amplitude): as 'motion' with 8 seasonal-amplitude bins on [-10, 10] mm "
+                            "(L=4096), P=32768"),
     "superres": (8, "double-scatterer simulations: N=29 over a 269.5 m aperture, L=256 bins on "
                     "[-80, 80] m, two unit scatterers kappa rho_s apart; 24 cases (kappa 1.2/0.8/0.4/0.2 "
                     "at 10/3/0 dB with random phase difference; kappa 0.2..1.2 at 2 and 7 dB with phase "
@@ -64,8 +67,10 @@ PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s
 # minimiser for the parity sample (strided over the whole stack); about 10-30 s
 # of host work each on 16 cores
 CPU_SAMPLE = {"scene": 16384, "pairs": 4096, "tiny": 1024, "motion": 4096, "motion_fine": 2048,
+              "motion_seasonal": 256,
               "superres": 16384}
 PARITY_SAMPLE = {"scene": 1024, "pairs": 512, "tiny": 1024, "motion": 512, "motion_fine": 256,
+                 "motion_seasonal": 64,
                  "superres": 960}
 PARITY_BAR = {"fp32": 1e-4, "split_bf16": 1e-3}
 POLISH_AFTER = 12          # FP32 iterations before a pixel goes to the FP64 stage

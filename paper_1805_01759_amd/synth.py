@@ -242,6 +242,10 @@ def uniform_draws(count: int, seed: int = 0) -> np.ndarray:
 # velocity grid and A gains one column per grid point.  Column c = i + Ls j holds
 # exp(-j 2 pi (xi_n s_i + eta_n v_j)) (elevation the fast index), i.e. A is the
 # column-wise Kronecker product of the elevation and velocity steering matrices.
+# A seasonal component (Eq. (4) with the temporal base function sin(2 pi t), period
+# one year) adds zeta_n = 2 sin(2 pi t_n) / lambda_w and a third axis of seasonal
+# amplitudes a_k: column i + Ls j + Ls Lv k holds exp(-j 2 pi (xi_n s_i + eta_n v_j +
+# zeta_n a_k)); with one seasonal level at a = 0 it is the elevation x velocity grid.
 
 @dataclasses.dataclass
 class MotionSpec:
@@ -256,10 +260,13 @@ class MotionSpec:
     s_hi: float = 60.0
     v_lo: float = -0.04   # m / year
     v_hi: float = 0.04
+    la: int = 1           # seasonal-amplitude bins (1: no seasonal axis)
+    a_lo: float = 0.0     # m
+    a_hi: float = 0.0
 
     @property
     def l(self) -> int:
-        return self.ls * self.lv
+        return self.ls * self.lv * self.la
 
 
 @dataclasses.dataclass
@@ -273,11 +280,14 @@ class MotionGeometry:
     eta: np.ndarray        # (N,) cycles per (metre / year) of velocity
     s: np.ndarray          # (Ls,) elevation grid, m
     v: np.ndarray          # (Lv,) velocity grid, m / year
-    A: np.ndarray          # (N, Ls Lv) complex128
+    A: np.ndarray          # (N, Ls Lv La) complex128
+    la: int = 1
+    zeta: np.ndarray | None = None  # (N,) cycles per metre of seasonal amplitude
+    a: np.ndarray | None = None     # (La,) seasonal-amplitude grid, m
 
     @property
     def l(self) -> int:
-        return self.ls * self.lv
+        return self.ls * self.lv * self.la
 
 
 MOTION_SPECS = {
@@ -285,12 +295,18 @@ MOTION_SPECS = {
     6: MotionSpec(6, 50, 32, 16, 1 << 19),
     # the same stack on a finer elevation grid: 64 x 16 = 1024 bins
     7: MotionSpec(7, 50, 64, 16, 1 << 16),
+    # elevation x velocity x seasonal amplitude (up to 10 mm): 32 x 16 x 8 = 4096 bins
+    10: MotionSpec(10, 50, 32, 16, 1 << 15, la=8, a_lo=-0.01, a_hi=0.01),
 }
 
 
-def motion_steering(geom: MotionGeometry, s: np.ndarray, v: np.ndarray) -> np.ndarray:
-    """exp(-j 2 pi (xi_n s + eta_n v)) for arrays s, v of one shape (..., ) -> (..., N)."""
-    return np.exp(-2j * np.pi * (np.multiply.outer(s, geom.xi) + np.multiply.outer(v, geom.eta)))
+def motion_steering(geom: MotionGeometry, s: np.ndarray, v: np.ndarray, a: np.ndarray | None = None) -> np.ndarray:
+    """exp(-j 2 pi (xi_n s + eta_n v + zeta_n a)) for arrays s, v (, a) of one shape
+    (..., ) -> (..., N); without a seasonal axis the last term is absent."""
+    ph = np.multiply.outer(s, geom.xi) + np.multiply.outer(v, geom.eta)
+    if a is not None and geom.zeta is not None:
+        ph = ph + np.multiply.outer(a, geom.zeta)
+    return np.exp(-2j * np.pi * ph)
 
 
 def make_motion_geometry(spec: MotionSpec, stack: int = 0) -> MotionGeometry:
@@ -301,9 +317,16 @@ def make_motion_geometry(spec: MotionSpec, stack: int = 0) -> MotionGeometry:
     eta = 2.0 * t / WAVELENGTH
     s = np.linspace(spec.s_lo, spec.s_hi, spec.ls)
     v = np.linspace(spec.v_lo, spec.v_hi, spec.lv)
-    ss, vv = np.meshgrid(s, v)            # (Lv, Ls): column c = i + Ls j
     geom = MotionGeometry(spec.n, spec.ls, spec.lv, b, t, xi, eta, s, v, None)
-    geom.A = np.ascontiguousarray(motion_steering(geom, ss.ravel(), vv.ravel()).T)
+    if spec.la == 1:
+        ss, vv = np.meshgrid(s, v)            # (Lv, Ls): column c = i + Ls j
+        geom.A = np.ascontiguousarray(motion_steering(geom, ss.ravel(), vv.ravel()).T)
+        return geom
+    geom.la = spec.la
+    geom.zeta = 2.0 * np.sin(2.0 * np.pi * t) / WAVELENGTH
+    geom.a = np.linspace(spec.a_lo, spec.a_hi, spec.la)
+    aa, vv, ss = np.meshgrid(geom.a, v, s, indexing="ij")  # (La, Lv, Ls): c = i + Ls j + Ls Lv k
+    geom.A = np.ascontiguousarray(motion_steering(geom, ss.ravel(), vv.ravel(), aa.ravel()).T)
     return geom
 
 
@@ -319,16 +342,20 @@ def _motion_block_pixels(spec: MotionSpec, geom: MotionGeometry, block: int, cou
     snr = g.uniform(0.0, 20.0, size=count)
     sigma2 = 10.0 ** (-snr / 10.0)
     noise = _cn(g, (count, spec.n)) * np.sqrt(sigma2)[:, None]
-    B = np.einsum("pk,pkn->pn", amp, motion_steering(geom, elev, vel)) + noise
+    # seasonal amplitudes (drawn last, so that stacks without the axis keep their draws)
+    seas = g.uniform(spec.a_lo, spec.a_hi, size=(count, 2)) if spec.la > 1 else None
+    B = np.einsum("pk,pkn->pn", amp, motion_steering(geom, elev, vel, seas)) + noise
     lam = np.sqrt(sigma2) * math.sqrt(2.0 * spec.n * math.log(spec.l))
     meta = {"k": k, "elev": elev, "vel": vel, "amp": amp, "snr_db": snr}
+    if seas is not None:
+        meta["seas"] = seas
     return B, lam, meta
 
 
 def make_motion_config(cfg: int, p0: int = 0, p1: int | None = None, with_meta: bool = False,
                        p_override: int | None = None):
     """Spec, geometry, B (P, N) complex128 and lambda (P,) of pixels [p0, p1) of a
-    multicomponent stack (configuration 6 or 7)."""
+    multicomponent stack (configuration 6, 7 or, with the seasonal axis, 10)."""
     spec = dataclasses.replace(MOTION_SPECS[cfg])
     if p_override is not None:
         spec.p = p_override

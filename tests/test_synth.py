@@ -132,3 +132,23 @@ def test_superres_cases():
     _, B2, _, meta2 = synth.make_superres(100, r0=250)
     for c in range(ncase):
         assert np.array_equal(B2[c * 100:(c + 1) * 100], B[c * R + 250:c * R + 350])
+
+
+def test_seasonal_motion_matrix_is_kronecker_of_three_steerings():
+    """Eq. (4) with a seasonal component (base function sin(2 pi t)): column
+    i + Ls j + Ls Lv k of A is the product of the elevation, velocity and seasonal
+    steering vectors of (s_i, v_j, a_k), and the pixels follow the model."""
+    spec, geom, B, lam, meta = synth.make_motion_config(10, 0, 4000, with_meta=True)
+    assert geom.A.shape == (50, 4096) and spec.l == 4096 and B.shape == (4000, 50)
+    Es = np.exp(-2j * np.pi * np.outer(geom.xi, geom.s))
+    Ev = np.exp(-2j * np.pi * np.outer(geom.eta, geom.v))
+    Ea = np.exp(-2j * np.pi * np.outer(geom.zeta, geom.a))
+    want = (Es[:, None, None, :] * Ev[:, None, :, None] * Ea[:, :, None, None]).reshape(50, -1)
+    assert np.allclose(geom.A, want, atol=1e-12)
+    assert np.allclose(geom.zeta, 2 * np.sin(2 * np.pi * geom.times) / 0.031)
+    sig = np.einsum("pk,pkn->pn", meta["amp"],
+                    synth.motion_steering(geom, meta["elev"], meta["vel"], meta["seas"]))
+    ratio = np.mean(np.abs(B - sig) ** 2, axis=1) / 10 ** (-meta["snr_db"] / 10)
+    assert abs(np.mean(ratio) - 1.0) < 0.03
+    assert meta["seas"].min() >= -0.01 and meta["seas"].max() <= 0.01
+    assert np.allclose(lam, np.sqrt(10 ** (-meta["snr_db"] / 10)) * math.sqrt(2 * 50 * math.log(4096)))
