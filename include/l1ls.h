@@ -29,10 +29,10 @@
  *  - Numerical outcomes are not errors: per-pixel results are reported in
  *    l1ls_diag.status and the call returns L1LS_OK.
  *  - Supported sizes: 1 <= N <= 128, 1 <= L <= 4096, 0 <= P < 2^31 (the
- *    wave-per-pixel kernel, the FP64 continuation and the block form take up
- *    to 1,024 bins: above that, WAVE is refused, fp64_continue leaves the
- *    pixels a refinement pass cannot finish unsolved, and l1ls_solve_blocks
- *    refuses blocks of more than 1,024 columns).
+ *    wave-per-pixel kernel and the block form take up to 1,024 bins: above
+ *    that, WAVE is refused and l1ls_solve_blocks refuses blocks of more than
+ *    1,024 columns; the FP64 continuation keeps a pixel's vectors in the
+ *    workspace there, 96 KB a workgroup per 1,024 bins, and is much slower).
  */
 #ifndef L1LS_H
 #define L1LS_H

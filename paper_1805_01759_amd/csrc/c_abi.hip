@@ -27,8 +27,9 @@ static l1ls_status fail(l1ls_status st, const char *fmt, ...)
 
 // Largest supported shapes: the register-resident MFMA tile takes N <= 64,
 // L <= 512; the streamed MFMA tile every shape up to N = 128, L = 4096 (the
-// wave-per-pixel kernel up to L = 1024; the FP64 continuation and the block form
-// up to 1,024 bins, or columns a block).
+// wave-per-pixel kernel up to L = 1024, the block form up to 1,024 columns a
+// block; the FP64 continuation in registers up to 1,024 bins, beyond in
+// workspace slots).
 constexpr int kMaxNSolve = 128;
 constexpr int kMaxLSolve = 4096;
 

@@ -14,9 +14,14 @@ namespace l1ls {
 // of W <= 4 waves (one per SIMD) covers L <= 8 KB W.
 constexpr int kTile = 16;        // pixels per workgroup (MFMA N dimension)
 constexpr int kMaxWavesIter = 4;
-// The FP64 continuation of Algorithm 1 keeps a pixel's iterate in registers, 16
-// chunks of 64 bins: stacks of more bins are not continued.
+// The FP64 continuation of Algorithm 1 keeps a pixel's iterate in registers (up
+// to 16 chunks of 64 bins) and its history in LDS; beyond kContMaxL bins its six
+// L-vectors (x^k, x^{k-1}, G_k, G_{k-1}, x-bar, d) live in a workspace slot per
+// workgroup (kContGroups of them at most).
 constexpr int kContMaxL = 1024;
+constexpr int kContGroups = 1024;
+__host__ __device__ inline int64_t cont_groups_for(int64_t p) { return p < kContGroups ? p : kContGroups; }
+__host__ __device__ inline size_t cont_slot_bytes(int l_pad) { return (size_t)6 * l_pad * 16; }
 constexpr int kMaxN = 128;
 constexpr int kMaxZB = 16;       // ceil(2 N / 16) <= 16
 
@@ -158,7 +163,7 @@ __host__ __device__ inline size_t stream_tile_bytes(int l_pad) { return (size_t)
 // Workspace layout for one stack (byte offsets; every region 256-byte aligned).
 struct StackWorkspace {
     size_t a_packed, a_trans, a_bf16, consts, queue, work, status, iters, kkt32, polish_list, gram, blocks, resid,
-        overflow, hgram, cbuf, fstate, total;
+        overflow, hgram, cbuf, cstate, fstate, total;
 };
 __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, int64_t p)
 {
@@ -199,6 +204,9 @@ __host__ __device__ inline StackWorkspace stack_workspace_layout(int n, int l, i
     w.cbuf = off;
     const int64_t groups = p < kMaxRefineGroups ? p : kMaxRefineGroups;
     off = ws_align(off + (size_t)groups * l * sizeof(double2));
+    // the FP64 continuation's slots for stacks beyond kContMaxL bins
+    w.cstate = off;
+    if (l_pad > kContMaxL) off = ws_align(off + (size_t)cont_groups_for(p) * cont_slot_bytes(l_pad));
     // the streamed MFMA tile's iterate state comes last, where that kernel runs
     // the stack (stack_workspace_bytes)
     w.fstate = off;
@@ -314,8 +322,8 @@ __host__ __device__ inline PolishArgsDev polish_args_for(const StackDesc &d, con
     pa.list = tier == 1 ? oflow : plist;
     pa.R = (tier == 0 && d.keep_residual) ? (const float2 *)(d.ws + lay.resid) : nullptr;
     // tier 2 lists the pixels it leaves above tol for the FP64 continuation
-    // (queue[7]), when that runs (up to kContMaxL bins)
-    const bool cont = o.cont && lpad_for(d.l) <= kContMaxL;
+    // (queue[7]), when that runs
+    const bool cont = o.cont != 0;
     pa.overflow = tier == 0 ? oflow : (tier == 1 ? plist : (cont ? oflow : nullptr));
     pa.overflow_count = tier < 2 || cont ? queue + 3 + 2 * tier : nullptr;
     pa.status = (uint32_t *)(d.ws + lay.status);
