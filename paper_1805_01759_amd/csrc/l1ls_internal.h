@@ -19,7 +19,7 @@ constexpr int kMaxWavesIter = 4;
 // L-vectors (x^k, x^{k-1}, G_k, G_{k-1}, x-bar, d) live in a workspace slot per
 // workgroup (kContGroups of them at most).
 constexpr int kContMaxL = 1024;
-constexpr int kContGroups = 1024;
+constexpr int kContGroups = 4096;
 __host__ __device__ inline int64_t cont_groups_for(int64_t p) { return p < kContGroups ? p : kContGroups; }
 __host__ __device__ inline size_t cont_slot_bytes(int l_pad) { return (size_t)6 * l_pad * 16; }
 constexpr int kMaxN = 128;
