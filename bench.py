@@ -511,7 +511,8 @@ def main():
         args.polish_after = polish_after_for(args.workload)
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (pixels are "
-              "independent; see the sharding note in DESIGN.md). Run with --gpus 1.",
+              "independent problems, so a stack would shard by pixel range with a copy of A "
+              "on every GPU). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
