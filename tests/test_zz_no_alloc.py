@@ -100,5 +100,7 @@ def test_noalloc_register_tile_fallback():
     assert sz.value <= _lib.NOALLOC_SCRATCH_BYTES  # the register tile's
     for prec in ("fp32", "split_bf16"):
         X0, d0, X1, d1 = _both(A, B, lam, polish_after=4, precision=prec)
+        differ = (torch.view_as_real(X0) != torch.view_as_real(X1)).any(dim=2).any(dim=1)
+        assert int(differ.sum()) == 0, (prec, int(differ.sum()), differ.nonzero()[:8].flatten().tolist())
         _same(X0, d0, X1, d1)
         assert ((d1["status"] & 1) != 0).float().mean().item() > 0.99
